@@ -1,0 +1,218 @@
+/*
+ * pfbspec -- polyphase-filter-bank spectrometer on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  Plain pointers and sizes only; no C++ or framework
+ * types cross this boundary.  Device pointers are HIP device addresses on
+ * the plan's device; host pointers are ordinary process memory.
+ *
+ * What one plan computes (A GPU-Based Wide-Band Radio Spectrometer, Section 4,
+ * with the initialisation / per-block loop of its high-level algorithm):
+ *
+ *   input   : a stream of 8-bit complex samples, one or two polarisations,
+ *             int8 x[t][pol][2] (time-major; re then im; two's complement);
+ *   filter  : spectrum j is the N-point DFT of
+ *               y_j[n] = sum_{p<P} h[p*N + n] * x[(j+p)*N + n]
+ *             (P-tap polyphase filter bank, hop N); in direct mode y_j is
+ *             frame j itself (no filter);
+ *   FFT     : X_j[k] = sum_n y_j[n] exp(-2 pi i k n / N), natural order;
+ *   products: |X|^2 for one polarisation; |X|^2, |Y|^2, Re(X Y*), Im(X Y*)
+ *             for two (Section 4);
+ *   dumps   : the products summed over n_int consecutive valid spectra
+ *             ("accumulate spectra for desired duration").
+ *
+ * Spectrum j = 0 is the first one whose P frames have all arrived; earlier
+ * partial windows are not emitted.  The last P-1 frames of every block are
+ * kept by the plan (the "tap history") so that the stream may be cut into
+ * blocks of any whole number of frames.
+ *
+ * Threading: a plan is not thread-safe; calls on one plan must be ordered on
+ * one stream.  Distinct plans are independent.  Every call is asynchronous
+ * with respect to the host unless stated otherwise.
+ *
+ * Errors: every call returns a status; no exception crosses the ABI.
+ * Arguments are validated before any state changes, so a rejected call leaves
+ * the plan as it was.  A failure reported by the HIP runtime marks the plan
+ * poisoned: later calls return PFBS_ERR_STATE until pfbs_plan_reset().
+ * pfbs_last_error() describes the most recent failure of the calling thread.
+ */
+#ifndef PFBSPEC_H
+#define PFBSPEC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfbs_plan pfbs_plan;    /* opaque; owns all device state of one stream */
+typedef struct pfbs_batch pfbs_batch;  /* opaque; several plans run by one launch sequence */
+
+typedef enum {
+    PFBS_OK = 0,
+    PFBS_ERR_INVALID = 1,     /* an argument is out of range or inconsistent   */
+    PFBS_ERR_UNSUPPORTED = 2, /* valid request this build cannot serve         */
+    PFBS_ERR_NOMEM = 3,       /* device or host allocation failed              */
+    PFBS_ERR_DEVICE = 4,      /* the HIP runtime reported an error             */
+    PFBS_ERR_STATE = 5        /* plan destroyed, poisoned, or used wrongly     */
+} pfbs_status;
+
+/* Prototype filter of the polyphase filter bank (Section 4 names an 8-tap PFB
+ * but not its coefficients):
+ *   HANN_SINC: h[m] = sinc((m - P*N/2)/N) * (1/2 - 1/2 cos(2 pi m/(P*N))),
+ *              sinc(u) = sin(pi u)/(pi u), no gain normalisation;
+ *   RECT     : h[m] = 1 (with P = 1 this reproduces direct mode);
+ *   CUSTOM   : P*N double coefficients supplied by the caller.            */
+typedef enum {
+    PFBS_WINDOW_HANN_SINC = 0,
+    PFBS_WINDOW_RECT = 1,
+    PFBS_WINDOW_CUSTOM = 2
+} pfbs_window;
+
+/* PFB: pre-filter then FFT.  DIRECT: FFT of each frame (P must be 1). */
+typedef enum { PFBS_MODE_PFB = 0, PFBS_MODE_DIRECT = 1 } pfbs_mode;
+
+/* Arithmetic of the FFT.  FP32: every stage on the vector ALUs in float.
+ * MFMA_FP16: radix-16 stages as 16x16 DFT-matrix products on the FP16 matrix
+ * cores with FP32 accumulation, single FP16 operands.  MFMA_FP16X2: the same
+ * with operands split into FP16 hi + lo pairs (three products per stage). */
+typedef enum {
+    PFBS_PREC_FP32 = 0,
+    PFBS_PREC_MFMA_FP16 = 1,
+    PFBS_PREC_MFMA_FP16X2 = 2
+} pfbs_precision;
+
+/* Full plan description.  Fields beyond the six of pfbs_plan_create:
+ *   precision   : see pfbs_precision;
+ *   custom_taps : host array of P*N doubles, read during the call only,
+ *                 required iff window == PFBS_WINDOW_CUSTOM, else ignored;
+ *   device      : HIP device ordinal, -1 = the calling thread's current one;
+ *   tune        : 0 = built-in heuristics, 1 = consult / fill the autotune
+ *                 cache (file named by PFBS_TUNE_CACHE, when set);
+ *   chunk       : spectra per partial integration (0 = automatic);
+ *   split_n2    : column length of the two-pass FFT (0 = automatic);
+ *   group_bytes : bound on the intermediate buffer of the two-pass FFT
+ *                 (0 = automatic).                                           */
+typedef struct {
+    int64_t N;
+    int32_t P;
+    int32_t window;     /* pfbs_window    */
+    int32_t mode;       /* pfbs_mode      */
+    int32_t n_pol;
+    int64_t n_int;
+    int32_t precision;  /* pfbs_precision */
+    int32_t device;
+    const double *custom_taps;
+    int32_t tune;
+    int32_t chunk;
+    int64_t split_n2;
+    int64_t group_bytes;
+} pfbs_plan_desc;
+
+/* Create a plan (FP32 arithmetic; Section 4, initialisation: coefficients are
+ * generated and loaded to the device, the FFT is planned).
+ *   N     : channels = FFT length, a power of two in [16, 2^20];
+ *   P     : taps (frames per spectrum), 1..16; must be 1 in DIRECT mode;
+ *   n_pol : 1 or 2 polarisations;
+ *   n_int : spectra per dump, >= 1.
+ * On success *out owns device memory for the taps, FFT tables, tap history
+ * and accumulators on the calling thread's current device.
+ * Returns PFBS_ERR_INVALID for bad arguments (checked before any HIP call). */
+pfbs_status pfbs_plan_create(pfbs_plan **out, int64_t N, int32_t P, int32_t window,
+                             int32_t mode, int32_t n_pol, int64_t n_int);
+
+/* Create a plan from a full description (see pfbs_plan_desc). */
+pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc);
+
+/* Release every resource of the plan.  Waits for the plan's queued work.
+ * NULL is accepted (no-op). */
+pfbs_status pfbs_plan_destroy(pfbs_plan *plan);
+
+/* Number of complete dumps that pfbs_execute would emit for the next block of
+ * n_time_samples samples (host arithmetic from the plan's counters; no device
+ * call).  Returns -1 if n_time_samples is not a positive multiple of N. */
+int64_t pfbs_dumps_in(const pfbs_plan *plan, int64_t n_time_samples);
+
+/* Process one block of the stream (Section 4, loop: pre-filter, parallel FFTs,
+ * accumulate).
+ *   d_block        : device, int8 [n_time_samples][n_pol][2], 16-byte aligned,
+ *                    read only, must stay valid until the stream reaches the
+ *                    work;
+ *   n_time_samples : a positive multiple of N;
+ *   d_dumps        : device, float [dump_capacity][n_prod][N] with n_prod = 1
+ *                    (one polarisation) or 4 (|X|^2, |Y|^2, Re XY*, Im XY*),
+ *                    product-major, channels in natural order; may be NULL
+ *                    when no dump completes;
+ *   dump_capacity  : dumps the buffer can hold; must be >= pfbs_dumps_in();
+ *   n_dumps_written: host, set to the number of dumps this call writes
+ *                    (known at return, no synchronisation);
+ *   stream         : hipStream_t (NULL = default stream).
+ * Dumps not yet complete stay in the plan's accumulators and continue with
+ * the next block. */
+pfbs_status pfbs_execute(pfbs_plan *plan, const void *d_block, int64_t n_time_samples,
+                         float *d_dumps, int64_t dump_capacity, int64_t *n_dumps_written,
+                         void *stream);
+
+/* Write the partial integration (spectra accumulated since the last dump) to
+ * d_partial (device, float [n_prod][N]) and its spectrum count to *n_spectra
+ * (host).  The plan's state is unchanged. */
+pfbs_status pfbs_flush(pfbs_plan *plan, float *d_partial, int64_t *n_spectra, void *stream);
+
+/* Forget the stream: clear the tap history, accumulators and counters, and
+ * clear the poisoned flag.  Synchronises with the plan's device. */
+pfbs_status pfbs_plan_reset(pfbs_plan *plan);
+
+/* Test hook: the FP32 pre-filter output y_j[n] of the spectra that the next
+ * block would complete, without changing the plan.  d_y: device,
+ * float [n_spectra][n_pol][N][2]; *n_spectra (host) receives the count.
+ * Same device code as the pre-filter inside pfbs_execute. */
+pfbs_status pfbs_debug_pfb(pfbs_plan *plan, const void *d_block, int64_t n_time_samples,
+                           float *d_y, int64_t y_capacity_spectra, int64_t *n_spectra,
+                           void *stream);
+
+/* Test hook: copy the plan's FP32 filter taps h[P*N] to d_out (device). */
+pfbs_status pfbs_debug_taps(pfbs_plan *plan, float *d_out, void *stream);
+
+/* Read-only plan facts for callers and tests (host, no device call). */
+typedef struct {
+    int64_t N;
+    int32_t P, n_pol, n_prod, mode, precision, chunk;
+    int64_t n_int;
+    int64_t split_n1, split_n2;     /* split_n1 == 1: single-pass FFT          */
+    int64_t frames_seen;            /* frames consumed so far                  */
+    int64_t spectra_done;           /* valid spectra produced so far           */
+    int64_t dumps_done;             /* dumps emitted so far                    */
+    int64_t device_bytes;           /* device memory held by the plan          */
+} pfbs_plan_info;
+
+pfbs_status pfbs_plan_get_info(const pfbs_plan *plan, pfbs_plan_info *info);
+
+/* Human-readable detail of the calling thread's last failure ("" if none). */
+const char *pfbs_last_error(void);
+
+/* Batched form: several independent sub-band streams (each with its own N, P,
+ * mode, n_int and state) processed by one fixed launch sequence per block,
+ * in the eight-sub-band spirit of the paper's 16 parallel FFTs (Section 4,
+ * initialisation) and its remark on per-batch launch overhead (Section 5).
+ *   descs: host array of n plan descriptions (all n_pol equal).             */
+pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int32_t n);
+
+/* One block per sub-band: d_blocks[i] (device) holds n_time_samples[i]
+ * samples for sub-band i; d_dumps[i] / caps[i] / n_dumps[i] as in
+ * pfbs_execute.  With use_graph != 0 the launch sequence is captured once in
+ * a HIP graph and replayed. */
+pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks,
+                               const int64_t *n_time_samples, float *const *d_dumps,
+                               const int64_t *caps, int64_t *n_dumps, int32_t use_graph,
+                               void *stream);
+
+/* Release the batch and the plans it owns.  NULL is accepted. */
+pfbs_status pfbs_batch_destroy(pfbs_batch *b);
+
+/* The plan of sub-band i of a batch (owned by the batch), or NULL. */
+pfbs_plan *pfbs_batch_plan(pfbs_batch *b, int32_t i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFBSPEC_H */

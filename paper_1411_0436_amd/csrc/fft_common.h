@@ -1,0 +1,262 @@
+// Device building blocks shared by the FFT kernels: complex arithmetic, the
+// radix-2/4/8/16 DFTs, the compile-time sub-FFT geometry, the Stockham passes
+// in LDS, int8 unpacking and the polarisation products.
+#pragma once
+
+#include "pfbs_internal.h"
+
+namespace pfbs {
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// --------------------------------------------------------------- complex --
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+    return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // a * (-i)
+
+// Forward DFTs (kernel e^{-2 pi i k n / R}), natural order in and out.
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+    float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    float2 t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+__device__ __forceinline__ void dft2(float2 *v) {
+    float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+// 8 = 2 x 4: n = m + 2r, k = q + 4s.
+__device__ __forceinline__ void dft8(float2 *v) {
+    const float h = 0.70710678118654752440f;
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    o1 = make_float2((o1.x + o1.y) * h, (o1.y - o1.x) * h);   // * W8^1
+    o2 = mul_mi(o2);                                         // * W8^2
+    o3 = make_float2((o3.y - o3.x) * h, -(o3.x + o3.y) * h);  // * W8^3
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// 16 = 4 x 4: n = m + 4r, k = q + 4s; inner twiddle W16^(m q).
+__device__ __forceinline__ void dft16(float2 *v) {
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    const float h = 0.70710678118654752440f;
+    float2 u[16];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        float2 a0 = v[m], a1 = v[m + 4], a2 = v[m + 8], a3 = v[m + 12];
+        dft4(a0, a1, a2, a3);
+        u[m * 4 + 0] = a0; u[m * 4 + 1] = a1; u[m * 4 + 2] = a2; u[m * 4 + 3] = a3;
+    }
+    u[5] = cmul(u[5], make_float2(c1, -s1));                                 // W^1
+    u[6] = make_float2((u[6].x + u[6].y) * h, (u[6].y - u[6].x) * h);        // W^2
+    u[7] = cmul(u[7], make_float2(s1, -c1));                                 // W^3
+    u[9] = make_float2((u[9].x + u[9].y) * h, (u[9].y - u[9].x) * h);        // W^2
+    u[10] = mul_mi(u[10]);                                                   // W^4
+    u[11] = make_float2((u[11].y - u[11].x) * h, -(u[11].x + u[11].y) * h);  // W^6
+    u[13] = cmul(u[13], make_float2(s1, -c1));                               // W^3
+    u[14] = make_float2((u[14].y - u[14].x) * h, -(u[14].x + u[14].y) * h);  // W^6
+    u[15] = cmul(u[15], make_float2(-c1, s1));                               // W^9
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float2 b0 = u[q], b1 = u[4 + q], b2 = u[8 + q], b3 = u[12 + q];
+        dft4(b0, b1, b2, b3);
+        v[q] = b0; v[q + 4] = b1; v[q + 8] = b2; v[q + 12] = b3;
+    }
+}
+
+template <int R> __device__ __forceinline__ void dftR(float2 *v);
+template <> __device__ __forceinline__ void dftR<2>(float2 *v) { dft2(v); }
+template <> __device__ __forceinline__ void dftR<4>(float2 *v) { dft4(v[0], v[1], v[2], v[3]); }
+template <> __device__ __forceinline__ void dftR<8>(float2 *v) { dft8(v); }
+
+// -------------------------------------------------------------- geometry --
+
+// Batched sub-FFT of length L = r0 * 16^n16 over T = 4096/L columns per
+// polarisation.  LDS: re and im planes [pol][c][Lp], element e of a column at
+// e + e/16 (one pad word per 16) and one more pad word per column, which keeps
+// the strided pass writes and the column-crossing reads free of bank conflicts.
+template <int L_>
+struct Geom {
+    static constexpr int L = L_;
+    static constexpr int logL = ilog2c(L);
+    static constexpr int T = kTilePoints / L;
+    static constexpr int logT = ilog2c(T);
+    static constexpr int n16 = logL / 4;
+    static constexpr int r0 = 1 << (logL % 4);
+    static constexpr int L16 = L / 16;
+    static constexpr int Lp = L + L / 16 + 1;
+    static constexpr int plane = T * Lp;  // floats of one polarisation plane
+    __device__ __forceinline__ static int idx(int pol, int c, int e) {
+        return (pol * T + c) * Lp + e + (e >> 4);
+    }
+    // Offset of radix-16 pass i in the twiddle table (Ns = r0 * 16^i entries each of 15).
+    static constexpr int tw_off(int i) { return i == 0 ? 0 : tw_off(i - 1) + r0 * (1 << (4 * (i - 1))) * 15; }
+};
+
+// First pass, radix R in {2,4,8}, sub-transform size 1 (no twiddle).  Thread
+// lt (0..255) of polarisation pol does 16/R butterflies.
+template <class G, int R>
+__device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int lt) {
+    constexpr int PER = 16 / R;
+    constexpr int logLR = G::logL - ilog2c(R);
+    constexpr int LR = 1 << logLR;
+    float2 v[PER][R];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const int b = lt + s * kBlockPol;
+        const int c = b >> logLR, bb = b & (LR - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int a = G::idx(pol, c, bb + r * LR);
+            v[s][r] = make_float2(sre[a], sim[a]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const int b = lt + s * kBlockPol;
+        const int c = b >> logLR, bb = b & (LR - 1);
+        dftR<R>(v[s]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int a = G::idx(pol, c, bb * R + r);
+            sre[a] = v[s][r].x;
+            sim[a] = v[s][r].y;
+        }
+    }
+    __syncthreads();
+}
+
+// Radix-16 pass i (sub-transform size Ns = r0*16^i): butterfly bb of column c
+// reads elements bb + r*L/16, applies W_(16 Ns)^(k r) with k = bb mod Ns, and
+// (except in the last pass) writes element (bb-k)*16 + k + r*Ns.
+template <class G, int I>
+__device__ __forceinline__ void pass16(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                       float2 (&v)[16]) {
+    constexpr int Ns = G::r0 * (1 << (4 * I));
+    constexpr bool LAST = I == G::n16 - 1;
+    const int c = lt >> (G::logL - 4), bb = lt & (G::L16 - 1);
+    const int k = bb & (Ns - 1);
+    float2 w[16];
+    if (Ns > 1) {
+        const float2 *t = tw + G::tw_off(I) + k * 15;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w[r] = t[r - 1];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int a = G::idx(pol, c, bb + r * G::L16);
+        v[r] = make_float2(sre[a], sim[a]);
+    }
+    __syncthreads();
+    if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+    }
+    dft16(v);
+    if (!LAST) {
+        const int base = ((bb - k) << 4) + k;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int a = G::idx(pol, c, base + r * Ns);
+            sre[a] = v[r].x;
+            sim[a] = v[r].y;
+        }
+        __syncthreads();
+    }
+}
+
+template <class G, int I>
+__device__ __forceinline__ void passes16(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                         float2 (&v)[16]) {
+    pass16<G, I>(sre, sim, pol, lt, tw, v);
+    if constexpr (I + 1 < G::n16) passes16<G, I + 1>(sre, sim, pol, lt, tw, v);
+}
+
+// Whole batched FFT of the columns of one polarisation plane held in LDS.
+// On return thread lt holds X_c[bb + r*L/16], r = 0..15, with
+// c = lt / (L/16), bb = lt mod (L/16).  Every thread of the workgroup must
+// call it (it contains workgroup barriers).
+template <class G>
+__device__ __forceinline__ void fft_plane(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                          float2 (&v)[16]) {
+    if constexpr (G::r0 > 1) pass_small<G, G::r0>(sre, sim, pol, lt);
+    passes16<G, 0>(sre, sim, pol, lt, tw, v);
+}
+
+// ---------------------------------------------------------------- unpack --
+
+// One time sample: NPOL complex int8 values, two's complement, exact in float.
+template <int NPOL> struct Sample;
+template <> struct Sample<2> {
+    typedef uint32_t word;
+    __device__ __forceinline__ static void unpack(word w, float2 (&x)[2]) {
+        x[0] = make_float2((float)(int8_t)(w & 0xff), (float)(int8_t)((w >> 8) & 0xff));
+        x[1] = make_float2((float)(int8_t)((w >> 16) & 0xff), (float)(int8_t)(w >> 24));
+    }
+};
+template <> struct Sample<1> {
+    typedef uint16_t word;
+    __device__ __forceinline__ static void unpack(word w, float2 (&x)[1]) {
+        x[0] = make_float2((float)(int8_t)(w & 0xff), (float)(int8_t)(w >> 8));
+    }
+};
+
+// Base address of frame f (block if f >= fs, else tap history).
+template <int NPOL>
+__device__ __forceinline__ const typename Sample<NPOL>::word *frame_ptr(const Frames &fr, long long f,
+                                                                        long long N) {
+    typedef typename Sample<NPOL>::word W;
+    return f >= fr.fs ? reinterpret_cast<const W *>(fr.blk) + (f - fr.fs) * N
+                      : reinterpret_cast<const W *>(fr.hist) + (f - fr.hf0) * N;
+}
+
+// y += h * x for one tap; taps are applied in order p = 0..P-1 starting from
+// y = 0, so the first one is y = h*x exactly rounded.
+template <int NPOL>
+__device__ __forceinline__ void tap_fma(float2 (&y)[NPOL], float h, typename Sample<NPOL>::word w) {
+    float2 x[NPOL];
+    Sample<NPOL>::unpack(w, x);
+#pragma unroll
+    for (int pol = 0; pol < NPOL; ++pol) {
+        y[pol].x = fmaf(h, x[pol].x, y[pol].x);
+        y[pol].y = fmaf(h, x[pol].y, y[pol].y);
+    }
+}
+
+// -------------------------------------------------------------- chunks ----
+
+__device__ __forceinline__ void chunk_range(const Chunks &ch, long long gid, long long &js,
+                                            long long &je) {
+    const long long d = gid / ch.C, c = gid - d * ch.C;
+    js = d * ch.n_int + c * ch.G;
+    je = min(js + (long long)ch.G, (d + 1) * ch.n_int);
+    js = max(js, ch.j_lo);
+    je = min(je, ch.j_hi);
+}
+
+// ------------------------------------------------------------- products ---
+
+// |X|^2, |Y|^2, Re X Y*, Im X Y* (Section 4 of the paper).
+__device__ __forceinline__ void prod4(float (&acc)[4], float2 X, float2 Y) {
+    acc[0] += X.x * X.x + X.y * X.y;
+    acc[1] += Y.x * Y.x + Y.y * Y.y;
+    acc[2] += X.x * Y.x + X.y * Y.y;
+    acc[3] += X.y * Y.x - X.x * Y.y;
+}
+
+}  // namespace pfbs

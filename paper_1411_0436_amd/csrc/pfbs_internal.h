@@ -1,0 +1,100 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+// Not part of the public ABI (include/pfbspec.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfbs {
+
+constexpr int kBlockPol = 256;       // threads per polarisation in the FFT kernels
+constexpr int kTilePoints = 4096;    // T * L: complex points per polarisation per workgroup step
+constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
+
+// Runtime view of the batched sub-FFT geometry (the kernels take L as a
+// template parameter; the host keeps these facts and the twiddle table).
+struct Geo {
+    int L;
+    int T;                // kTilePoints / L sequences per workgroup step
+    const float2 *tw;     // radix-16 pass twiddles, passes concatenated
+};
+
+// Spectrum-chunk enumeration.  Dump d covers global spectra
+// [d*n_int, (d+1)*n_int); each dump is cut into C = ceil(n_int/G) chunks of
+// G spectra; global chunk id = d*C + c.  A launch covers chunk ids
+// [gid0, gid0 + n_chunks) and spectra [j_lo, j_hi).
+struct Chunks {
+    long long n_int;
+    long long C;
+    int G;
+    long long j_lo, j_hi;     // spectra of the whole block
+    long long gid_lo;         // first chunk id of the block (partial index base)
+    long long gid0;           // first chunk id of this launch
+};
+
+// Frame addressing of the stream: frame f lives in the block if f >= fs,
+// otherwise in the tap history whose first frame is hf0.
+struct Frames {
+    const uint8_t *blk;
+    const uint8_t *hist;
+    long long fs, hf0;
+};
+
+struct FrontArgs {
+    Frames fr;
+    const float *taps;        // h[P][N]
+    Geo g;
+    long long N, N1, N2;      // N1 == 1: single pass (whole FFT here)
+    int P;
+    int ntiles;               // column tiles along n1 (four-step pass A)
+    Chunks ch;
+    // pass-A output
+    float2 *Z;                // [spectra of launch][pol][N2][N1]
+    long long jz0;            // spectrum index of Z[0]
+    const float2 *t4lo, *t4hi;
+    int q4;                   // W_N^m = t4lo[m & (2^q4-1)] * t4hi[m >> q4]
+    // single-pass output
+    float *part;              // [chunks of block][n_prod][N]
+};
+
+struct BackArgs {
+    const float2 *Z;
+    long long jz0;
+    Geo g;                    // L = N1
+    long long N, N1, N2;
+    int ntiles;               // row tiles along k2
+    Chunks ch;
+    float *part;              // [chunks of block][n_prod][N], index u = k2*N1 + k1
+};
+
+struct ReduceArgs {
+    const float *part;
+    float *carried;           // [n_prod][N], internal order u
+    float *out;               // [dumps][n_prod][N], natural order k
+    long long N, N1, N2;      // u = k2*N1 + k1  <->  k = k2 + N2*k1 (N2 == 1: identity)
+    int n_prod;
+    long long n_int, C;
+    int G;
+    long long j_lo, j_hi, gid_lo, gid_hi, d_lo;
+    int flush;                // 1: out[q][k] = carried (or 0 if !have_carried)
+    int have_carried;
+};
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_tables_taps(float *h, long long N, int P, int window, const double *d_custom,
+                              hipStream_t s);
+hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s);
+hipError_t launch_tables_tw4(float2 *lo, float2 *hi, long long N, int q4, hipStream_t s);
+hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_chunks,
+                        hipStream_t s);
+hipError_t launch_back(const BackArgs &a, int npol, int n_chunks, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s);
+hipError_t launch_history(uint8_t *dst, const Frames &fr, long long F, int H, long long frame_bytes,
+                          hipStream_t s);
+hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long long N, int P,
+                            int npol, bool pfb, long long j_lo, long long j_hi, hipStream_t s);
+hipError_t kernels_init();   // raise LDS limits once per process/device
+size_t front_lds_bytes(const Geo &g, int npol);
+size_t back_lds_bytes(const Geo &g, int npol);
+
+}  // namespace pfbs

@@ -1,0 +1,672 @@
+// Host side of the spectrometer library: plan objects, argument validation,
+// block / spectrum / dump bookkeeping and the launch sequence per block.
+//
+// The split follows the paper's high-level algorithm (Section 4): plan
+// creation is its initialisation (filter coefficients to the device, FFT
+// planned for the parallel transforms), pfbs_execute is one turn of its loop
+// (pre-filter, parallel FFTs, accumulation) on a block that is already in
+// device memory.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pfbspec.h"
+#include "pfbs_internal.h"
+
+using namespace pfbs;
+
+namespace {
+
+thread_local std::string g_err;
+
+pfbs_status fail(pfbs_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+constexpr uint32_t kMagic = 0x50464253u;  // "PFBS"
+constexpr uint32_t kDead = 0xdeadbeefu;
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+Geo make_geo(int L) {
+    Geo g{};
+    g.L = L;
+    g.T = kTilePoints / L;
+    g.tw = nullptr;
+    return g;
+}
+
+// Entries of the radix-16 pass twiddle table for length L = r0 * 16^n16:
+// sum over passes of Ns*15 with Ns = r0, 16 r0, ...
+int64_t tw16_count(const Geo &g) {
+    const int logL = ilog2(g.L);
+    int64_t n = 0, Ns = int64_t(1) << (logL % 4);
+    for (int i = 0; i < logL / 4; ++i) {
+        n += Ns * 15;
+        Ns *= 16;
+    }
+    return n;
+}
+
+std::mutex g_init_mu;
+bool g_init_done[64];
+
+}  // namespace
+
+struct pfbs_plan {
+    uint32_t magic;
+    // description
+    int64_t N;
+    int32_t P;
+    int32_t window, mode, npol, precision, device;
+    int64_t n_int;
+    int32_t nprod;
+    bool pfb;
+    // geometry
+    bool fourstep;
+    int64_t N1, N2;
+    Geo gA, gB;
+    int ntilesA, ntilesB;
+    int G;
+    int64_t C;
+    int q4;
+    int64_t group_spectra;
+    // device state
+    float *taps;
+    float2 *twA, *twB, *t4lo, *t4hi;
+    uint8_t *hist[2];
+    int hcur;
+    int64_t frame_bytes;
+    float2 *Z;
+    size_t Zcap;      // float2 elements
+    float *part;
+    size_t partcap;   // floats
+    float *carried;
+    int64_t device_bytes;
+    // stream counters
+    int64_t frames_seen, spectra_done, dumps_done;
+    bool poisoned;
+};
+
+struct pfbs_batch {
+    uint32_t magic;
+    std::vector<pfbs_plan *> plans;
+};
+
+namespace {
+
+pfbs_status hip_fail(pfbs_plan *p, hipError_t e, const char *what) {
+    if (p) p->poisoned = true;
+    return fail(e == hipErrorOutOfMemory ? PFBS_ERR_NOMEM : PFBS_ERR_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define PFBS_HIP(p, call)                                   \
+    do {                                                    \
+        hipError_t _e = (call);                             \
+        if (_e != hipSuccess) return hip_fail((p), _e, #call); \
+    } while (0)
+
+// Column length N2 (pass A) and row length N1 = N/N2 (pass B) of the
+// two-pass FFT: both must have kernels built for them and tile evenly.
+bool split_ok(int64_t N, int64_t n2) {
+    if (!is_pow2(n2) || n2 < 64 || n2 > 512) return false;
+    const int64_t n1 = N / n2;
+    if (n1 < 32 || n1 > kMaxSinglePass) return false;
+    return n1 % (kTilePoints / n2) == 0 && n2 % (kTilePoints / n1) == 0;
+}
+
+pfbs_status validate_desc(const pfbs_plan_desc *d) {
+    if (!d) return fail(PFBS_ERR_INVALID, "desc is NULL");
+    if (!is_pow2(d->N) || d->N < 16 || d->N > (int64_t(1) << 20))
+        return fail(PFBS_ERR_INVALID, "N=%lld must be a power of two in [16, 2^20]", (long long)d->N);
+    if (d->P < 1 || d->P > 16) return fail(PFBS_ERR_INVALID, "P=%d must be in [1, 16]", d->P);
+    if (d->mode != PFBS_MODE_PFB && d->mode != PFBS_MODE_DIRECT)
+        return fail(PFBS_ERR_INVALID, "unknown mode %d", d->mode);
+    if (d->mode == PFBS_MODE_DIRECT && d->P != 1)
+        return fail(PFBS_ERR_INVALID, "direct mode requires P=1 (got %d)", d->P);
+    if (d->window != PFBS_WINDOW_HANN_SINC && d->window != PFBS_WINDOW_RECT &&
+        d->window != PFBS_WINDOW_CUSTOM)
+        return fail(PFBS_ERR_INVALID, "unknown window %d", d->window);
+    if (d->mode == PFBS_MODE_PFB && d->window == PFBS_WINDOW_CUSTOM && !d->custom_taps)
+        return fail(PFBS_ERR_INVALID, "custom window needs custom_taps");
+    if (d->n_pol != 1 && d->n_pol != 2) return fail(PFBS_ERR_INVALID, "n_pol=%d must be 1 or 2", d->n_pol);
+    if (d->n_int < 1) return fail(PFBS_ERR_INVALID, "n_int=%lld must be >= 1", (long long)d->n_int);
+    if (d->precision != PFBS_PREC_FP32 && d->precision != PFBS_PREC_MFMA_FP16 &&
+        d->precision != PFBS_PREC_MFMA_FP16X2)
+        return fail(PFBS_ERR_INVALID, "unknown precision %d", d->precision);
+    if (d->chunk < 0 || d->chunk > 65536) return fail(PFBS_ERR_INVALID, "chunk=%d out of range", d->chunk);
+    if (d->split_n2 != 0) {
+        if (d->N <= kMaxSinglePass)
+            return fail(PFBS_ERR_INVALID, "split_n2 given but N=%lld is done in one pass", (long long)d->N);
+        if (!split_ok(d->N, d->split_n2))
+            return fail(PFBS_ERR_INVALID, "split_n2=%lld invalid for N=%lld (column length 64..512, "
+                        "row length 32..4096)", (long long)d->split_n2, (long long)d->N);
+    }
+    if (d->group_bytes < 0) return fail(PFBS_ERR_INVALID, "group_bytes < 0");
+    return PFBS_OK;
+}
+
+// Spectra of global chunk gid intersected with [j_lo, j_hi).
+void chunk_span(const pfbs_plan *p, int64_t gid, int64_t j_lo, int64_t j_hi, int64_t &js, int64_t &je) {
+    const int64_t d = gid / p->C, c = gid - d * p->C;
+    js = d * p->n_int + c * p->G;
+    je = std::min(js + (int64_t)p->G, (d + 1) * p->n_int);
+    js = std::max(js, j_lo);
+    je = std::min(je, j_hi);
+}
+
+int64_t chunk_of(const pfbs_plan *p, int64_t j) {
+    const int64_t d = j / p->n_int;
+    return d * p->C + (j - d * p->n_int) / p->G;
+}
+
+// Spectra [j_lo, j_hi) completed by a block of F frames.
+void block_spectra(const pfbs_plan *p, int64_t F, int64_t &j_lo, int64_t &j_hi) {
+    const int64_t need = p->pfb ? p->P : 1;
+    j_lo = p->spectra_done;
+    j_hi = std::max<int64_t>(0, p->frames_seen + F - need + 1);
+    if (j_hi < j_lo) j_hi = j_lo;
+}
+
+bool plan_ok(const pfbs_plan *p) { return p && p->magic == kMagic; }
+
+template <typename T>
+hipError_t dalloc(pfbs_plan *p, T **ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+    if (e == hipSuccess) p->device_bytes += (int64_t)(count * sizeof(T));
+    return e;
+}
+
+void free_plan_memory(pfbs_plan *p) {
+    void *bufs[] = {p->taps, p->twA, p->twB, p->t4lo, p->t4hi, p->hist[0], p->hist[1],
+                    p->Z, p->part, p->carried};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+pfbs_status ensure_scratch(pfbs_plan *p, size_t z_elems, size_t part_floats) {
+    if (z_elems > p->Zcap) {
+        if (p->Z) {
+            (void)hipFree(p->Z);
+            p->device_bytes -= (int64_t)(p->Zcap * sizeof(float2));
+            p->Z = nullptr;
+            p->Zcap = 0;
+        }
+        PFBS_HIP(p, dalloc(p, &p->Z, z_elems));
+        p->Zcap = z_elems;
+    }
+    if (part_floats > p->partcap) {
+        if (p->part) {
+            (void)hipFree(p->part);
+            p->device_bytes -= (int64_t)(p->partcap * sizeof(float));
+            p->part = nullptr;
+            p->partcap = 0;
+        }
+        PFBS_HIP(p, dalloc(p, &p->part, part_floats));
+        p->partcap = part_floats;
+    }
+    return PFBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pfbs_last_error(void) { return g_err.c_str(); }
+
+pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
+    if (!out) return fail(PFBS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    pfbs_status st = validate_desc(desc);
+    if (st != PFBS_OK) return st;
+    if (desc->precision != PFBS_PREC_FP32)
+        return fail(PFBS_ERR_UNSUPPORTED, "precision %d is not available in this build", desc->precision);
+
+    int dev = desc->device;
+    if (dev < 0) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    } else {
+        hipError_t e = hipSetDevice(dev);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    }
+    if (dev < 0 || dev >= 64) return fail(PFBS_ERR_UNSUPPORTED, "device ordinal %d", dev);
+    {
+        std::lock_guard<std::mutex> lk(g_init_mu);
+        if (!g_init_done[dev]) {
+            hipError_t e = kernels_init();
+            if (e != hipSuccess) return hip_fail(nullptr, e, "kernel attributes");
+            g_init_done[dev] = true;
+        }
+    }
+
+    pfbs_plan *p = new (std::nothrow) pfbs_plan();
+    if (!p) return fail(PFBS_ERR_NOMEM, "host allocation");
+    p->magic = kMagic;
+    p->N = desc->N;
+    p->pfb = desc->mode == PFBS_MODE_PFB;
+    p->P = p->pfb ? desc->P : 1;
+    p->window = desc->window;
+    p->mode = desc->mode;
+    p->npol = desc->n_pol;
+    p->precision = desc->precision;
+    p->device = dev;
+    p->n_int = desc->n_int;
+    p->nprod = p->npol == 2 ? 4 : 1;
+    p->fourstep = p->N > kMaxSinglePass;
+    if (p->fourstep) {
+        p->N2 = desc->split_n2 ? desc->split_n2 : 256;
+        p->N1 = p->N / p->N2;
+        p->gA = make_geo((int)p->N2);
+        p->gB = make_geo((int)p->N1);
+        p->ntilesA = (int)(p->N1 / p->gA.T);
+        p->ntilesB = (int)(p->N2 / p->gB.T);
+    } else {
+        p->N1 = 1;
+        p->N2 = p->N;
+        p->gA = make_geo((int)p->N);
+        p->ntilesA = 1;
+        p->ntilesB = 0;
+    }
+    if (desc->chunk > 0) p->G = desc->chunk;
+    else p->G = p->fourstep ? 16 : std::max(16, p->gA.T);
+    p->C = (p->n_int + p->G - 1) / p->G;
+    p->q4 = (ilog2(p->N) + 1) / 2;
+    const int64_t zbytes_per_spec = (int64_t)p->npol * p->N * (int64_t)sizeof(float2);
+    const int64_t gb = desc->group_bytes > 0 ? desc->group_bytes : (int64_t(1) << 30);
+    p->group_spectra = std::max<int64_t>(p->G, gb / zbytes_per_spec);
+    p->frame_bytes = p->N * 2 * p->npol;
+
+    hipStream_t s = nullptr;
+    double *d_custom = nullptr;
+    pfbs_status rs = PFBS_OK;
+    hipError_t e = hipSuccess;
+    do {
+        if ((e = dalloc(p, &p->taps, (size_t)p->P * p->N)) != hipSuccess) break;
+        if ((e = dalloc(p, &p->twA, (size_t)tw16_count(p->gA))) != hipSuccess) break;
+        p->gA.tw = p->twA;
+        if (p->fourstep) {
+            if ((e = dalloc(p, &p->twB, (size_t)tw16_count(p->gB))) != hipSuccess) break;
+            p->gB.tw = p->twB;
+            if ((e = dalloc(p, &p->t4lo, (size_t)1 << p->q4)) != hipSuccess) break;
+            if ((e = dalloc(p, &p->t4hi, (size_t)(p->N >> p->q4))) != hipSuccess) break;
+        }
+        const size_t hbytes = (size_t)(p->P - 1) * p->frame_bytes;
+        if (p->P > 1) {
+            if ((e = dalloc(p, &p->hist[0], hbytes)) != hipSuccess) break;
+            if ((e = dalloc(p, &p->hist[1], hbytes)) != hipSuccess) break;
+            if ((e = hipMemsetAsync(p->hist[0], 0, hbytes, s)) != hipSuccess) break;
+        }
+        if ((e = dalloc(p, &p->carried, (size_t)p->nprod * p->N)) != hipSuccess) break;
+        if ((e = hipMemsetAsync(p->carried, 0, (size_t)p->nprod * p->N * sizeof(float), s)) != hipSuccess) break;
+        int window = p->pfb ? p->window : PFBS_WINDOW_RECT;
+        if (window == PFBS_WINDOW_CUSTOM) {
+            const size_t n = (size_t)p->P * p->N;
+            if ((e = hipMalloc((void **)&d_custom, n * sizeof(double))) != hipSuccess) break;
+            if ((e = hipMemcpy(d_custom, desc->custom_taps, n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+        }
+        if ((e = launch_tables_taps(p->taps, p->N, p->P, window, d_custom, s)) != hipSuccess) break;
+        if ((e = launch_tables_tw16(p->twA, p->gA.L, s)) != hipSuccess) break;
+        if (p->fourstep) {
+            if ((e = launch_tables_tw16(p->twB, p->gB.L, s)) != hipSuccess) break;
+            if ((e = launch_tables_tw4(p->t4lo, p->t4hi, p->N, p->q4, s)) != hipSuccess) break;
+        }
+        if ((e = hipDeviceSynchronize()) != hipSuccess) break;
+    } while (0);
+    if (d_custom) (void)hipFree(d_custom);
+    if (e != hipSuccess) {
+        rs = hip_fail(nullptr, e, "plan creation");
+        free_plan_memory(p);
+        p->magic = kDead;
+        delete p;
+        return rs;
+    }
+    *out = p;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_plan_create(pfbs_plan **out, int64_t N, int32_t P, int32_t window, int32_t mode,
+                             int32_t n_pol, int64_t n_int) {
+    pfbs_plan_desc d;
+    memset(&d, 0, sizeof d);
+    d.N = N;
+    d.P = P;
+    d.window = window;
+    d.mode = mode;
+    d.n_pol = n_pol;
+    d.n_int = n_int;
+    d.precision = PFBS_PREC_FP32;
+    d.device = -1;
+    return pfbs_plan_create_ex(out, &d);
+}
+
+pfbs_status pfbs_plan_destroy(pfbs_plan *p) {
+    if (!p) return PFBS_OK;
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    free_plan_memory(p);
+    p->magic = kDead;
+    delete p;
+    return PFBS_OK;
+}
+
+int64_t pfbs_dumps_in(const pfbs_plan *p, int64_t n) {
+    if (!plan_ok(p) || n <= 0 || n % p->N != 0) return -1;
+    int64_t j_lo, j_hi;
+    block_spectra(p, n / p->N, j_lo, j_hi);
+    return j_hi / p->n_int - j_lo / p->n_int;
+}
+
+pfbs_status pfbs_plan_get_info(const pfbs_plan *p, pfbs_plan_info *info) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    if (!info) return fail(PFBS_ERR_INVALID, "info is NULL");
+    memset(info, 0, sizeof *info);
+    info->N = p->N;
+    info->P = p->P;
+    info->n_pol = p->npol;
+    info->n_prod = p->nprod;
+    info->mode = p->mode;
+    info->precision = p->precision;
+    info->chunk = p->G;
+    info->n_int = p->n_int;
+    info->split_n1 = p->N1;
+    info->split_n2 = p->N2;
+    info->frames_seen = p->frames_seen;
+    info->spectra_done = p->spectra_done;
+    info->dumps_done = p->dumps_done;
+    info->device_bytes = p->device_bytes;
+    return PFBS_OK;
+}
+
+static pfbs_status check_block(const pfbs_plan *p, const void *d_block, int64_t n) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    if (p->poisoned) return fail(PFBS_ERR_STATE, "plan is poisoned by an earlier device error; reset it");
+    if (!d_block) return fail(PFBS_ERR_INVALID, "d_block is NULL");
+    if (((uintptr_t)d_block & 15) != 0) return fail(PFBS_ERR_INVALID, "d_block must be 16-byte aligned");
+    if (n <= 0 || n % p->N != 0)
+        return fail(PFBS_ERR_INVALID, "n_time_samples=%lld must be a positive multiple of N=%lld",
+                    (long long)n, (long long)p->N);
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps, int64_t cap,
+                         int64_t *n_written, void *stream) {
+    pfbs_status st = check_block(p, d_block, n);
+    if (st != PFBS_OK) return st;
+    if (!n_written) return fail(PFBS_ERR_INVALID, "n_dumps_written is NULL");
+    const int64_t F = n / p->N;
+    int64_t j_lo, j_hi;
+    block_spectra(p, F, j_lo, j_hi);
+    const int64_t nd_out = j_hi / p->n_int - j_lo / p->n_int;
+    if (nd_out > 0 && !d_dumps) return fail(PFBS_ERR_INVALID, "d_dumps is NULL but %lld dumps complete", (long long)nd_out);
+    if (cap < nd_out)
+        return fail(PFBS_ERR_INVALID, "dump_capacity=%lld < %lld dumps completed by this block",
+                    (long long)cap, (long long)nd_out);
+    *n_written = 0;
+    hipStream_t s = (hipStream_t)stream;
+    PFBS_HIP(p, hipSetDevice(p->device));
+
+    Frames fr;
+    fr.blk = (const uint8_t *)d_block;
+    fr.hist = p->hist[p->hcur];
+    fr.fs = p->frames_seen;
+    fr.hf0 = p->frames_seen - (p->P - 1);
+
+    if (j_hi > j_lo) {
+        const int64_t gid_lo = chunk_of(p, j_lo), gid_hi = chunk_of(p, j_hi - 1);
+        const int64_t n_chunks = gid_hi - gid_lo + 1;
+        Chunks ch;
+        ch.n_int = p->n_int;
+        ch.C = p->C;
+        ch.G = p->G;
+        ch.j_lo = j_lo;
+        ch.j_hi = j_hi;
+        ch.gid_lo = gid_lo;
+        ch.gid0 = gid_lo;
+        size_t zneed = 0;
+        if (p->fourstep) {
+            const int64_t gs = std::min<int64_t>(p->group_spectra, j_hi - j_lo + p->G);
+            zneed = (size_t)(gs + p->G) * p->npol * p->N;
+        }
+        st = ensure_scratch(p, zneed, (size_t)n_chunks * p->nprod * p->N);
+        if (st != PFBS_OK) return st;
+
+        FrontArgs fa;
+        memset(&fa, 0, sizeof fa);
+        fa.fr = fr;
+        fa.taps = p->taps;
+        fa.g = p->gA;
+        fa.N = p->N;
+        fa.N1 = p->N1;
+        fa.N2 = p->N2;
+        fa.P = p->P;
+        fa.ntiles = p->ntilesA;
+        fa.ch = ch;
+        fa.Z = p->Z;
+        fa.t4lo = p->t4lo;
+        fa.t4hi = p->t4hi;
+        fa.q4 = p->q4;
+        fa.part = p->part;
+        if (!p->fourstep) {
+            PFBS_HIP(p, launch_front(fa, p->npol, p->pfb, true, (int)n_chunks, s));
+        } else {
+            BackArgs ba;
+            memset(&ba, 0, sizeof ba);
+            ba.Z = p->Z;
+            ba.g = p->gB;
+            ba.N = p->N;
+            ba.N1 = p->N1;
+            ba.N2 = p->N2;
+            ba.ntiles = p->ntilesB;
+            ba.ch = ch;
+            ba.part = p->part;
+            // groups of whole chunks whose intermediate fits the Z buffer
+            const int64_t zlimit = std::min<int64_t>(
+                (int64_t)(p->Zcap / ((size_t)p->npol * p->N)), std::max<int64_t>(p->group_spectra, p->G));
+            int64_t g0 = gid_lo;
+            while (g0 <= gid_hi) {
+                int64_t gjs, gje, tjs, tje;
+                chunk_span(p, g0, j_lo, j_hi, gjs, gje);
+                int64_t g1 = g0;
+                while (g1 + 1 <= gid_hi) {
+                    chunk_span(p, g1 + 1, j_lo, j_hi, tjs, tje);
+                    if (tje - gjs > zlimit) break;
+                    ++g1;
+                    gje = tje;
+                }
+                fa.ch.gid0 = g0;
+                fa.jz0 = gjs;
+                ba.ch.gid0 = g0;
+                ba.jz0 = gjs;
+                const int nc = (int)(g1 - g0 + 1);
+                PFBS_HIP(p, launch_front(fa, p->npol, p->pfb, false, nc, s));
+                PFBS_HIP(p, launch_back(ba, p->npol, nc, s));
+                g0 = g1 + 1;
+            }
+        }
+        ReduceArgs ra;
+        memset(&ra, 0, sizeof ra);
+        ra.part = p->part;
+        ra.carried = p->carried;
+        ra.out = d_dumps;
+        ra.N = p->N;
+        ra.N1 = p->N1;
+        ra.N2 = p->fourstep ? p->N2 : 1;
+        ra.n_prod = p->nprod;
+        ra.n_int = p->n_int;
+        ra.C = p->C;
+        ra.G = p->G;
+        ra.j_lo = j_lo;
+        ra.j_hi = j_hi;
+        ra.gid_lo = gid_lo;
+        ra.gid_hi = gid_hi;
+        ra.d_lo = j_lo / p->n_int;
+        const int64_t d_hi = (j_hi - 1) / p->n_int;
+        PFBS_HIP(p, launch_reduce(ra, (int)(d_hi - ra.d_lo + 1), s));
+    }
+    if (p->pfb && p->P > 1) {
+        PFBS_HIP(p, launch_history(p->hist[p->hcur ^ 1], fr, F, p->P - 1, p->frame_bytes, s));
+        p->hcur ^= 1;
+    }
+    p->frames_seen += F;
+    p->spectra_done = j_hi;
+    p->dumps_done += nd_out;
+    *n_written = nd_out;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_flush(pfbs_plan *p, float *d_partial, int64_t *n_spectra, void *stream) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    if (p->poisoned) return fail(PFBS_ERR_STATE, "plan is poisoned");
+    if (!d_partial || !n_spectra) return fail(PFBS_ERR_INVALID, "NULL argument");
+    PFBS_HIP(p, hipSetDevice(p->device));
+    const int64_t cnt = p->spectra_done - p->dumps_done * p->n_int;
+    ReduceArgs ra;
+    memset(&ra, 0, sizeof ra);
+    ra.carried = p->carried;
+    ra.out = d_partial;
+    ra.N = p->N;
+    ra.N1 = p->N1;
+    ra.N2 = p->fourstep ? p->N2 : 1;
+    ra.n_prod = p->nprod;
+    ra.n_int = p->n_int;
+    ra.C = p->C;
+    ra.flush = 1;
+    ra.have_carried = cnt > 0;
+    PFBS_HIP(p, launch_reduce(ra, 1, (hipStream_t)stream));
+    *n_spectra = cnt;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_plan_reset(pfbs_plan *p) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    hipError_t e = hipSetDevice(p->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(p, e, "reset");
+    p->frames_seen = 0;
+    p->spectra_done = 0;
+    p->dumps_done = 0;
+    p->hcur = 0;
+    p->poisoned = false;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_debug_pfb(pfbs_plan *p, const void *d_block, int64_t n, float *d_y, int64_t ycap,
+                           int64_t *n_spectra, void *stream) {
+    pfbs_status st = check_block(p, d_block, n);
+    if (st != PFBS_OK) return st;
+    if (!n_spectra || !d_y) return fail(PFBS_ERR_INVALID, "NULL argument");
+    int64_t j_lo, j_hi;
+    block_spectra(p, n / p->N, j_lo, j_hi);
+    if (ycap < j_hi - j_lo)
+        return fail(PFBS_ERR_INVALID, "y capacity %lld < %lld spectra", (long long)ycap, (long long)(j_hi - j_lo));
+    *n_spectra = j_hi - j_lo;
+    if (j_hi == j_lo) return PFBS_OK;
+    PFBS_HIP(p, hipSetDevice(p->device));
+    Frames fr;
+    fr.blk = (const uint8_t *)d_block;
+    fr.hist = p->hist[p->hcur];
+    fr.fs = p->frames_seen;
+    fr.hf0 = p->frames_seen - (p->P - 1);
+    PFBS_HIP(p, launch_debug_pfb(d_y, fr, p->taps, p->N, p->P, p->npol, p->pfb, j_lo, j_hi,
+                                 (hipStream_t)stream));
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_debug_taps(pfbs_plan *p, float *d_out, void *stream) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    if (!d_out) return fail(PFBS_ERR_INVALID, "d_out is NULL");
+    PFBS_HIP(p, hipSetDevice(p->device));
+    PFBS_HIP(p, hipMemcpyAsync(d_out, p->taps, (size_t)p->P * p->N * sizeof(float),
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return PFBS_OK;
+}
+
+// ---------------------------------------------------------------- batch ----
+
+pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int32_t n) {
+    if (!out) return fail(PFBS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!descs || n < 1 || n > 64) return fail(PFBS_ERR_INVALID, "need 1..64 descriptions");
+    for (int i = 0; i < n; ++i) {
+        pfbs_status st = validate_desc(&descs[i]);
+        if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
+        if (descs[i].n_pol != descs[0].n_pol) return fail(PFBS_ERR_INVALID, "all sub-bands need the same n_pol");
+    }
+    pfbs_batch *b = new (std::nothrow) pfbs_batch();
+    if (!b) return fail(PFBS_ERR_NOMEM, "host allocation");
+    b->magic = kMagic;
+    for (int i = 0; i < n; ++i) {
+        pfbs_plan *p = nullptr;
+        pfbs_status st = pfbs_plan_create_ex(&p, &descs[i]);
+        if (st != PFBS_OK) {
+            std::string why = g_err;
+            for (pfbs_plan *q : b->plans) pfbs_plan_destroy(q);
+            delete b;
+            return fail(st, "sub-band %d: %s", i, why.c_str());
+        }
+        b->plans.push_back(p);
+    }
+    *out = b;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const int64_t *n_samples,
+                               float *const *d_dumps, const int64_t *caps, int64_t *n_dumps,
+                               int32_t use_graph, void *stream) {
+    if (!b || b->magic != kMagic) return fail(PFBS_ERR_STATE, "not a live batch");
+    if (!d_blocks || !n_samples || !d_dumps || !caps || !n_dumps) return fail(PFBS_ERR_INVALID, "NULL argument");
+    (void)use_graph;
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i) {
+        pfbs_status st = check_block(b->plans[i], d_blocks[i], n_samples[i]);
+        if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
+        const int64_t nd = pfbs_dumps_in(b->plans[i], n_samples[i]);
+        if (caps[i] < nd || (nd > 0 && !d_dumps[i]))
+            return fail(PFBS_ERR_INVALID, "sub-band %d: dump capacity %lld < %lld", i, (long long)caps[i], (long long)nd);
+    }
+    for (int i = 0; i < n; ++i) {
+        pfbs_status st = pfbs_execute(b->plans[i], d_blocks[i], n_samples[i], d_dumps[i], caps[i],
+                                      &n_dumps[i], stream);
+        if (st != PFBS_OK) return st;
+    }
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_batch_destroy(pfbs_batch *b) {
+    if (!b) return PFBS_OK;
+    if (b->magic != kMagic) return fail(PFBS_ERR_STATE, "not a live batch");
+    for (pfbs_plan *p : b->plans) pfbs_plan_destroy(p);
+    b->magic = kDead;
+    delete b;
+    return PFBS_OK;
+}
+
+pfbs_plan *pfbs_batch_plan(pfbs_batch *b, int32_t i) {
+    if (!b || b->magic != kMagic || i < 0 || i >= (int32_t)b->plans.size()) return nullptr;
+    return b->plans[i];
+}
+
+}  // extern "C"

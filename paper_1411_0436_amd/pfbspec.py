@@ -1,0 +1,238 @@
+"""Python binding of the pfbspec C ABI (include/pfbspec.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the spectrometer runs in the library's HIP kernels.
+There is no fallback: if libpfbspec.so is missing or fails to load, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfbspec.so")
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOMEM, ERR_DEVICE, ERR_STATE = range(6)
+WINDOW_HANN_SINC, WINDOW_RECT, WINDOW_CUSTOM = 0, 1, 2
+MODE_PFB, MODE_DIRECT = 0, 1
+PREC_FP32, PREC_MFMA_FP16, PREC_MFMA_FP16X2 = 0, 1, 2
+
+# Every entry point declared in include/pfbspec.h.
+EXPORTS = (
+    "pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_dumps_in",
+    "pfbs_execute", "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
+    "pfbs_plan_get_info", "pfbs_last_error", "pfbs_batch_create", "pfbs_batch_execute",
+    "pfbs_batch_destroy", "pfbs_batch_plan",
+)
+
+
+class PfbsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("pfbspec status %d: %s" % (status, msg))
+        self.status = status
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("P", ctypes.c_int32), ("window", ctypes.c_int32),
+        ("mode", ctypes.c_int32), ("n_pol", ctypes.c_int32), ("n_int", ctypes.c_int64),
+        ("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("custom_taps", ctypes.c_void_p), ("tune", ctypes.c_int32), ("chunk", ctypes.c_int32),
+        ("split_n2", ctypes.c_int64), ("group_bytes", ctypes.c_int64),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("P", ctypes.c_int32), ("n_pol", ctypes.c_int32),
+        ("n_prod", ctypes.c_int32), ("mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("chunk", ctypes.c_int32), ("n_int", ctypes.c_int64), ("split_n1", ctypes.c_int64),
+        ("split_n2", ctypes.c_int64), ("frames_seen", ctypes.c_int64),
+        ("spectra_done", ctypes.c_int64), ("dumps_done", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpfbspec.so and declare the signatures.  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libpfbspec.so not built (%s); run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    L.pfbs_plan_create.argtypes = [ctypes.POINTER(vp), i64, i32, i32, i32, i32, i64]
+    L.pfbs_plan_create_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc)]
+    L.pfbs_plan_destroy.argtypes = [vp]
+    L.pfbs_dumps_in.argtypes = [vp, i64]
+    L.pfbs_dumps_in.restype = i64
+    L.pfbs_execute.argtypes = [vp, vp, i64, vp, i64, pi64, vp]
+    L.pfbs_flush.argtypes = [vp, vp, pi64, vp]
+    L.pfbs_plan_reset.argtypes = [vp]
+    L.pfbs_debug_pfb.argtypes = [vp, vp, i64, vp, i64, pi64, vp]
+    L.pfbs_debug_taps.argtypes = [vp, vp, vp]
+    L.pfbs_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.pfbs_last_error.restype = ctypes.c_char_p
+    L.pfbs_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), i32]
+    L.pfbs_batch_execute.argtypes = [vp, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64, pi64, i32, vp]
+    L.pfbs_batch_destroy.argtypes = [vp]
+    L.pfbs_batch_plan.argtypes = [vp, i32]
+    L.pfbs_batch_plan.restype = vp
+    for name in ("pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_execute",
+                 "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
+                 "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().pfbs_last_error().decode(errors="replace")
+
+
+def _check(st: int):
+    if st != OK:
+        raise PfbsError(st, last_error())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_PFB, n_pol: int = 2,
+              n_int: int = 1, precision: int = PREC_FP32, device: int = -1, custom_taps=None,
+              tune: int = 0, chunk: int = 0, split_n2: int = 0, group_bytes: int = 0):
+    """A PlanDesc; ``custom_taps`` (float64 numpy array) is kept alive on the
+    returned object until the plan is created."""
+    import numpy as np
+    d = PlanDesc(N=N, P=P, window=window, mode=mode, n_pol=n_pol, n_int=n_int,
+                 precision=precision, device=device, custom_taps=None, tune=tune,
+                 chunk=chunk, split_n2=split_n2, group_bytes=group_bytes)
+    keep = None
+    if custom_taps is not None:
+        keep = np.ascontiguousarray(custom_taps, dtype=np.float64)
+        if keep.size != N * P:
+            raise ValueError("custom_taps needs P*N values")
+        d.custom_taps = keep.ctypes.data
+    d._keep = keep
+    return d
+
+
+class Plan:
+    """One spectrometer stream (pfbs_plan)."""
+
+    def __init__(self, N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_PFB,
+                 n_pol: int = 2, n_int: int = 1, **kw):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        d = make_desc(N, P, window, mode, n_pol, n_int, **kw)
+        _check(self._lib.pfbs_plan_create_ex(ctypes.byref(self._h), ctypes.byref(d)))
+        self.N, self.P, self.n_pol, self.n_int = N, P, n_pol, n_int
+        self.n_prod = 4 if n_pol == 2 else 1
+
+    @classmethod
+    def _wrap(cls, handle: int, owner) -> "Plan":
+        self = cls.__new__(cls)
+        self._lib = load()
+        self._h = ctypes.c_void_p(handle)
+        self._owner = owner
+        i = self.info()
+        self.N, self.P, self.n_pol, self.n_int, self.n_prod = i["N"], i["P"], i["n_pol"], i["n_int"], i["n_prod"]
+        return self
+
+    def close(self):
+        if getattr(self, "_owner", None) is None and self._h:
+            _check(self._lib.pfbs_plan_destroy(self._h))
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dumps_in(self, n_time_samples: int) -> int:
+        return int(self._lib.pfbs_dumps_in(self._h, n_time_samples))
+
+    def execute(self, block, dumps=None, stream=None) -> int:
+        """block: int8 cuda tensor [n, n_pol, 2] (or flat); dumps: float32 cuda
+        tensor [cap, n_prod, N] or None.  Returns dumps written."""
+        n = block.numel() // (2 * self.n_pol)
+        cap = 0 if dumps is None else dumps.numel() // (self.n_prod * self.N)
+        out = ctypes.c_int64(0)
+        _check(self._lib.pfbs_execute(self._h, block.data_ptr(), n,
+                                      None if dumps is None else dumps.data_ptr(), cap,
+                                      ctypes.byref(out), _stream_ptr(stream)))
+        return out.value
+
+    def flush(self, partial, stream=None) -> int:
+        cnt = ctypes.c_int64(0)
+        _check(self._lib.pfbs_flush(self._h, partial.data_ptr(), ctypes.byref(cnt), _stream_ptr(stream)))
+        return cnt.value
+
+    def reset(self):
+        _check(self._lib.pfbs_plan_reset(self._h))
+
+    def debug_pfb(self, block, y, stream=None) -> int:
+        n = block.numel() // (2 * self.n_pol)
+        cap = y.numel() // (self.n_pol * self.N * 2)
+        cnt = ctypes.c_int64(0)
+        _check(self._lib.pfbs_debug_pfb(self._h, block.data_ptr(), n, y.data_ptr(), cap,
+                                        ctypes.byref(cnt), _stream_ptr(stream)))
+        return cnt.value
+
+    def debug_taps(self, out, stream=None):
+        _check(self._lib.pfbs_debug_taps(self._h, out.data_ptr(), _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(self._lib.pfbs_plan_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+
+class Batch:
+    """Several sub-band streams run by one launch sequence (pfbs_batch)."""
+
+    def __init__(self, descs: Sequence[PlanDesc]):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        arr = (PlanDesc * len(descs))(*descs)
+        _check(self._lib.pfbs_batch_create(ctypes.byref(self._h), arr, len(descs)))
+        self.n = len(descs)
+        self.plans = [Plan._wrap(self._lib.pfbs_batch_plan(self._h, i), self) for i in range(self.n)]
+
+    def execute(self, blocks, dumps, use_graph: bool = False, stream=None):
+        n = self.n
+        vp = ctypes.c_void_p
+        blk = (vp * n)(*[b.data_ptr() for b in blocks])
+        ns = (ctypes.c_int64 * n)(*[b.numel() // (2 * p.n_pol) for b, p in zip(blocks, self.plans)])
+        dp = (vp * n)(*[None if d is None else d.data_ptr() for d in dumps])
+        caps = (ctypes.c_int64 * n)(*[0 if d is None else d.numel() // (p.n_prod * p.N)
+                                      for d, p in zip(dumps, self.plans)])
+        nd = (ctypes.c_int64 * n)()
+        _check(self._lib.pfbs_batch_execute(self._h, blk, ns, dp, caps, nd, int(use_graph),
+                                            _stream_ptr(stream)))
+        return list(nd)
+
+    def close(self):
+        if self._h:
+            for p in self.plans:
+                p._h = ctypes.c_void_p()
+            _check(self._lib.pfbs_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
