@@ -186,6 +186,17 @@ typedef struct {
 
 pfbs_status pfbs_plan_get_info(const pfbs_plan *plan, pfbs_plan_info *info);
 
+/* Kernel timing.  With enable != 0 every kernel launch that pfbs_execute makes
+ * for this plan is bracketed by a pair of HIP events recorded on the execute
+ * stream.  pfbs_plan_timing_read waits for those events, adds their elapsed
+ * times (ms) and launch counts per kernel kind into ms[kind] / launches[kind]
+ * for kind < n (kinds: 0 single-pass, 1 column pass, 2 row pass, 3 dump
+ * reduction, 4 tap history; PFBS_KERNEL_KINDS in all), and forgets them.
+ * Intended for measurement; it adds two event records per launch. */
+#define PFBS_KERNEL_KINDS 5
+pfbs_status pfbs_plan_timing(pfbs_plan *plan, int32_t enable);
+pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches, int32_t n);
+
 /* Human-readable detail of the calling thread's last failure ("" if none). */
 const char *pfbs_last_error(void);
 

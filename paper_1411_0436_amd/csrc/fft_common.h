@@ -85,21 +85,26 @@ template <> __device__ __forceinline__ void dftR<8>(float2 *v) { dft8(v); }
 
 // -------------------------------------------------------------- geometry --
 
-// Batched sub-FFT of length L = r0 * 16^n16 over T = 4096/L columns per
-// polarisation.  LDS: re and im planes [pol][c][Lp], element e of a column at
-// e + e/16 (one pad word per 16) and one more pad word per column, which keeps
-// the strided pass writes and the column-crossing reads free of bank conflicts.
-template <int L_>
+// Batched sub-FFT of length L = r0 * 16^n16 over T = TP/L columns per
+// polarisation (TP complex points per polarisation per workgroup step, done by
+// TPP = TP/16 threads, each owning one radix-16 butterfly).  LDS: re and im
+// planes [pol][c][Lp], element e of a column at e + e/16 (one pad word per
+// 16) and one more pad word per column, which keeps the strided pass writes
+// and the column-crossing reads free of bank conflicts.
+template <int L_, int TP_ = kTilePoints>
 struct Geom {
     static constexpr int L = L_;
+    static constexpr int TP = TP_;
+    static constexpr int TPP = TP / 16;   // threads per polarisation
     static constexpr int logL = ilog2c(L);
-    static constexpr int T = kTilePoints / L;
+    static constexpr int T = TP / L;
     static constexpr int logT = ilog2c(T);
     static constexpr int n16 = logL / 4;
     static constexpr int r0 = 1 << (logL % 4);
     static constexpr int L16 = L / 16;
     static constexpr int Lp = L + L / 16 + 1;
     static constexpr int plane = T * Lp;  // floats of one polarisation plane
+    static_assert(T >= 1 && L >= 16, "sub-FFT geometry");
     __device__ __forceinline__ static int idx(int pol, int c, int e) {
         return (pol * T + c) * Lp + e + (e >> 4);
     }
@@ -108,7 +113,7 @@ struct Geom {
 };
 
 // First pass, radix R in {2,4,8}, sub-transform size 1 (no twiddle).  Thread
-// lt (0..255) of polarisation pol does 16/R butterflies.
+// lt (0..TPP-1) of polarisation pol does 16/R butterflies.
 template <class G, int R>
 __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int lt) {
     constexpr int PER = 16 / R;
@@ -117,7 +122,7 @@ __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int 
     float2 v[PER][R];
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-        const int b = lt + s * kBlockPol;
+        const int b = lt + s * G::TPP;
         const int c = b >> logLR, bb = b & (LR - 1);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -128,7 +133,7 @@ __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int 
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-        const int b = lt + s * kBlockPol;
+        const int b = lt + s * G::TPP;
         const int c = b >> logLR, bb = b & (LR - 1);
         dftR<R>(v[s]);
 #pragma unroll

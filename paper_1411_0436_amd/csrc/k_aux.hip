@@ -5,21 +5,25 @@
 namespace pfbs {
 
 hipError_t launch_front_single(const FrontArgs &a, int npol, bool pfb, int n_chunks, hipStream_t s);
-hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_chunks, hipStream_t s);
+hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_items, hipStream_t s);
 hipError_t init_single(int lds_limit);
 hipError_t init_fourstep(int lds_limit);
 
 // ------------------------------------------------------------- reduce -----
 
-// Dump d = d_lo + blockIdx.y: carried-in sum (if the dump began in an earlier
-// block) plus the chunk partials of this block in chunk order.  Complete
-// dumps go to out in channel order; an incomplete one back to carried.
-// Tile: 32 k2 x 32 k1 through LDS so both the partial reads (along k1) and
-// the dump writes (along k2) are coalesced.  Identity order when N2 == 1.
+// Dump d = d_lo + blockIdx.y, product q = blockIdx.z: carried-in sum (if the
+// dump began in an earlier block) plus the chunk partials of this block in
+// chunk order.  Complete dumps go to out in channel order; an incomplete one
+// (only the last) to carried_out, a different buffer from carried_in because
+// the first dump of the same launch may still be reading that one.
+// Four-step order (N2 > 1): a workgroup takes 8 k2 x 32 k1 (reads along k1,
+// one partial per thread), then writes channel order k = k2 + N2 k1 through
+// LDS.  Single pass (N2 == 1): 256 consecutive channels.
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
-    __shared__ float tile[32][33];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    __shared__ float tile[8][33];
+    const int t = threadIdx.x;
     const long long d = a.d_lo + blockIdx.y;
+    const int q = blockIdx.z;
     const long long g_first = max(a.gid_lo, d * a.C);
     const long long g_last = min(a.gid_hi, d * a.C + a.C - 1);
     const bool carried_in = a.flush ? (a.have_carried != 0) : (d * a.n_int < a.j_lo);
@@ -27,47 +31,44 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     const long long slot = d - a.d_lo;
     const long long N = a.N;
     const bool tr = a.N2 > 1;
-    long long k2b, k1b;  // tile origin
+    long long u;
+    long long k2b = 0, k1b = 0;
     if (tr) {
-        const long long nt2 = a.N2 / 32;
-        k2b = (blockIdx.x % nt2) * 32;
+        const long long nt2 = a.N2 / 8;
+        k2b = (blockIdx.x % nt2) * 8;
         k1b = (blockIdx.x / nt2) * 32;
+        u = (k2b + (t >> 5)) * a.N1 + k1b + (t & 31);
     } else {
-        k2b = 0;
-        k1b = (long long)blockIdx.x * 256;
+        u = (long long)blockIdx.x * 256 + t;
     }
-    for (int q = 0; q < a.n_prod; ++q) {
-        if (tr) {
+    float s = 0.f;
+    if (u < N) {
+        if (carried_in) s = a.carried_in[q * N + u];
+        if (!a.flush) {
+            const float *pp = a.part + q * N + u;
+            const long long stride = (long long)a.n_prod * N;
+            long long gg = g_first;
+            // batches of independent loads, added in chunk order
+            for (; gg + 8 <= g_last + 1; gg += 8) {
+                float v[8];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long long u = (k2b + ty + 8 * i) * a.N1 + k1b + tx;
-                float s = carried_in ? a.carried[q * N + u] : 0.f;
-                if (!a.flush)
-                    for (long long gg = g_first; gg <= g_last; ++gg)
-                        s += a.part[((gg - a.gid_lo) * a.n_prod + q) * N + u];
-                if (complete) tile[ty + 8 * i][tx] = s;
-                else a.carried[q * N + u] = s;
-            }
-            if (complete) {
-                __syncthreads();
+                for (int i = 0; i < 8; ++i) v[i] = pp[(gg + i - a.gid_lo) * stride];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const long long k = (k2b + tx) + a.N2 * (k1b + ty + 8 * i);
-                    a.out[(slot * a.n_prod + q) * N + k] = tile[tx][ty + 8 * i];
-                }
-                __syncthreads();
+                for (int i = 0; i < 8; ++i) s += v[i];
             }
-        } else {
-            const long long u = k1b + threadIdx.x;
-            if (u < N) {
-                float s = carried_in ? a.carried[q * N + u] : 0.f;
-                if (!a.flush)
-                    for (long long gg = g_first; gg <= g_last; ++gg)
-                        s += a.part[((gg - a.gid_lo) * a.n_prod + q) * N + u];
-                if (complete) a.out[(slot * a.n_prod + q) * N + u] = s;
-                else a.carried[q * N + u] = s;
-            }
+            for (; gg <= g_last; ++gg) s += pp[(gg - a.gid_lo) * stride];
         }
+        if (!complete) a.carried_out[q * N + u] = s;
+    }
+    if (!complete) return;
+    float *out = a.out + (slot * a.n_prod + q) * N;
+    if (tr) {
+        tile[t >> 5][t & 31] = s;
+        __syncthreads();
+        const int dk2 = t & 7, dk1 = t >> 3;
+        out[(k2b + dk2) + a.N2 * (k1b + dk1)] = tile[dk2][dk1];
+    } else if (u < N) {
+        out[u] = s;
     }
 }
 
@@ -164,16 +165,16 @@ __global__ void k_tw16(float2 *tw, int r0, int n16) {
     }
 }
 
-// Four-step twiddles: lo[m] = W_N^m (m < 2^q4), hi[m] = W_N^(m 2^q4).
-__global__ void k_tw4(float2 *lo, float2 *hi, long long N, int q4) {
-    const long long nlo = 1LL << q4, nhi = N >> q4;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nlo + nhi;
+// Four-step twiddles tw4[n1*N2 + k2] = W_N^(n1 k2), FP64 sincospi then FP32.
+__global__ void k_tw4(float2 *tw4, long long N1, long long N2) {
+    const long long N = N1 * N2;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
          e += (long long)gridDim.x * blockDim.x) {
-        const long long m = e < nlo ? e : (e - nlo) << q4;
+        const long long n1 = e / N2, k2 = e - n1 * N2;
+        const long long m = (n1 * k2) % N;
         double s, c;
         sincospi(-2.0 * (double)m / (double)N, &s, &c);
-        if (e < nlo) lo[e] = make_float2((float)c, (float)s);
-        else hi[e - nlo] = make_float2((float)c, (float)s);
+        tw4[e] = make_float2((float)c, (float)s);
     }
 }
 
@@ -199,8 +200,8 @@ hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tables_tw4(float2 *lo, float2 *hi, long long N, int q4, hipStream_t s) {
-    hipLaunchKernelGGL(k_tw4, dim3(16), dim3(256), 0, s, lo, hi, N, q4);
+hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_t s) {
+    hipLaunchKernelGGL(k_tw4, dim3(grid_for(N1 * N2, 256)), dim3(256), 0, s, tw4, N1, N2);
     return hipGetLastError();
 }
 
@@ -210,16 +211,16 @@ size_t front_lds_bytes(const Geo &g, int npol) {
 }
 size_t back_lds_bytes(const Geo &g, int npol) { return front_lds_bytes(g, npol); }
 
-hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_chunks,
+hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_items,
                         hipStream_t s) {
-    return single ? launch_front_single(a, npol, pfb, n_chunks, s)
-                  : launch_front_cols(a, npol, pfb, n_chunks, s);
+    return single ? launch_front_single(a, npol, pfb, n_items, s)
+                  : launch_front_cols(a, npol, pfb, n_items, s);
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s) {
     dim3 grid;
-    if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / 32) * (a.N1 / 32)), (unsigned)n_dumps);
-    else grid = dim3((unsigned)((a.N + 255) / 256), (unsigned)n_dumps);
+    if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / 8) * (a.N1 / 32)), (unsigned)n_dumps, (unsigned)a.n_prod);
+    else grid = dim3((unsigned)((a.N + 255) / 256), (unsigned)n_dumps, (unsigned)a.n_prod);
     hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }

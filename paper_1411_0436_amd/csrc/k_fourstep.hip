@@ -14,25 +14,26 @@
 namespace pfbs {
 
 template <int NPOL, bool PFB, int L>
-__global__ __launch_bounds__(kBlockPol *NPOL) void k_front_cols(FrontArgs a) {
+__global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArgs a) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
-    constexpr int NB = kBlockPol * NPOL;
+    constexpr int NB = G::TPP * NPOL;
     constexpr int PTS = kTilePoints / NB;
     extern __shared__ float smem[];
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
-    const int tid = threadIdx.x, pol = tid >> 8, lt = tid & (kBlockPol - 1);
+    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
     const int tile = blockIdx.x % a.ntiles;
-    const long long gid = a.ch.gid0 + blockIdx.x / a.ntiles;
-    long long js, je;
-    chunk_range(a.ch, gid, js, je);
+    // spectra [js, je): the item-th run of ga spectra of the launch's range
+    const long long js = a.sa0 + (long long)(blockIdx.x / a.ntiles) * a.ga;
+    const long long je = min(js + (long long)a.ga, a.sa1);
     const long long N = a.N;
     const int N1 = (int)a.N1;
     const int n1_0 = tile * G::T;
     const int P = PFB ? a.P : 1;
-    const int mask4 = (1 << a.q4) - 1;
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+    // W_N^(n1 k2) of this thread's column, k2 = bb + r*L/16
+    const float2 *tw4 = a.tw4 + (unsigned)((n1_0 + c_own) * L + bb_own);
 
     for (long long j = js; j < je; ++j) {
         float2 y[PTS][NPOL];
@@ -68,13 +69,10 @@ __global__ __launch_bounds__(kBlockPol *NPOL) void k_front_cols(FrontArgs a) {
         float2 v[16];
         fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
         // ---- twiddle W_N^(n1 k2), back to LDS in natural order
-        const int n1 = n1_0 + c_own;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int k2 = bb_own + r * G::L16;
-            const int m = n1 * k2;
-            const float2 w = cmul(a.t4lo[m & mask4], a.t4hi[m >> a.q4]);
-            const float2 z = cmul(v[r], w);
+            const float2 z = cmul(v[r], tw4[r * G::L16]);
             const int ad = G::idx(pol, c_own, k2);
             sre[ad] = z.x;
             sim[ad] = z.y;
@@ -95,16 +93,20 @@ __global__ __launch_bounds__(kBlockPol *NPOL) void k_front_cols(FrontArgs a) {
     }
 }
 
+// Row-pass tile: at least 1024 points per polarisation (64 threads each), so
+// short rows still give many small workgroups.
+template <int L> struct BackTile { static constexpr int TP = L < 1024 ? 1024 : L; };
+
 template <int NPOL, int L>
-__global__ __launch_bounds__(kBlockPol *NPOL) void k_back(BackArgs a) {
-    typedef Geom<L> G;
-    constexpr int NB = kBlockPol * NPOL;
+__global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a) {
+    typedef Geom<L, BackTile<L>::TP> G;
+    constexpr int NB = G::TPP * NPOL;
     constexpr int NP = NPOL == 2 ? 4 : 1;
-    constexpr int BINS = kTilePoints / NB;
+    constexpr int BINS = G::TP / NB;
     extern __shared__ float smem[];
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
-    const int tid = threadIdx.x, pol = tid >> 8, lt = tid & (kBlockPol - 1);
+    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
     const int tile = blockIdx.x % a.ntiles;
     const long long gid = a.ch.gid0 + blockIdx.x / a.ntiles;
     long long js, je;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(kBlockPol *NPOL) void k_back(BackArgs a) {
     for (long long j = js; j < je; ++j) {
         const float2 *zb = a.Z + (j - a.jz0) * NPOL * N;
 #pragma unroll
-        for (int s = 0; s < (NPOL * kTilePoints) / NB; ++s) {
+        for (int s = 0; s < (NPOL * G::TP) / NB; ++s) {
             const int i = tid + NB * s;
             const int n1 = i & (L - 1);
             const int cc = (i >> G::logL) & (G::T - 1);
@@ -176,9 +178,9 @@ __global__ __launch_bounds__(kBlockPol *NPOL) void k_back(BackArgs a) {
 #define PFBS_COLS_CASES(X) X(64) X(128) X(256) X(512)
 #define PFBS_BACK_CASES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
-hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_chunks, hipStream_t s) {
+hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_items, hipStream_t s) {
     const size_t lds = front_lds_bytes(a.g, npol);
-    const dim3 grid(n_chunks * a.ntiles), block(kBlockPol * npol);
+    const dim3 grid(n_items * a.ntiles), block(kTilePoints / 16 * npol);
     switch (a.g.L) {
 #define PFBS_CASE(LL)                                                                           \
     case LL:                                                                                    \
@@ -200,7 +202,7 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_chunk
 
 hipError_t launch_back(const BackArgs &a, int npol, int n_chunks, hipStream_t s) {
     const size_t lds = back_lds_bytes(a.g, npol);
-    const dim3 grid(n_chunks * a.ntiles), block(kBlockPol * npol);
+    const dim3 grid(n_chunks * a.ntiles), block(a.g.T * a.g.L / 16 * npol);
     switch (a.g.L) {
 #define PFBS_CASE(LL)                                                              \
     case LL:                                                                       \

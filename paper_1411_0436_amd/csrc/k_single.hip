@@ -13,17 +13,17 @@
 namespace pfbs {
 
 template <int NPOL, bool PFB, int L>
-__global__ __launch_bounds__(kBlockPol *NPOL) void k_front_single(FrontArgs a) {
+__global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_single(FrontArgs a) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
-    constexpr int NB = kBlockPol * NPOL;   // threads
+    constexpr int NB = G::TPP * NPOL;      // threads
     constexpr int PTS = kTilePoints / NB;  // pre-filter points per thread (all pols each)
     constexpr int NP = NPOL == 2 ? 4 : 1;  // products
     constexpr int BINS = kTilePoints / NB; // accumulated bins per thread
     extern __shared__ float smem[];
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
-    const int tid = threadIdx.x, pol = tid >> 8, lt = tid & (kBlockPol - 1);
+    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
     const long long gid = a.ch.gid0 + blockIdx.x;
     long long js, je;
     chunk_range(a.ch, gid, js, je);
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlockPol *NPOL) void k_front_single(FrontArgs a) {
 
 hipError_t launch_front_single(const FrontArgs &a, int npol, bool pfb, int n_chunks, hipStream_t s) {
     const size_t lds = front_lds_bytes(a.g, npol);
-    const dim3 grid(n_chunks), block(kBlockPol * npol);
+    const dim3 grid(n_chunks), block(kTilePoints / 16 * npol);
     switch (a.g.L) {
 #define PFBS_CASE(LL)                                                                              \
     case LL:                                                                                       \

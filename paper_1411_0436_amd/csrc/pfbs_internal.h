@@ -7,7 +7,6 @@
 
 namespace pfbs {
 
-constexpr int kBlockPol = 256;       // threads per polarisation in the FFT kernels
 constexpr int kTilePoints = 4096;    // T * L: complex points per polarisation per workgroup step
 constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
 
@@ -15,7 +14,7 @@ constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
 // template parameter; the host keeps these facts and the twiddle table).
 struct Geo {
     int L;
-    int T;                // kTilePoints / L sequences per workgroup step
+    int T;                // sequences per workgroup step (tile points / L)
     const float2 *tw;     // radix-16 pass twiddles, passes concatenated
 };
 
@@ -48,11 +47,12 @@ struct FrontArgs {
     int P;
     int ntiles;               // column tiles along n1 (four-step pass A)
     Chunks ch;
-    // pass-A output
+    // pass A: spectra [sa0, sa1) in runs of ga per workgroup
+    long long sa0, sa1;
+    int ga;
     float2 *Z;                // [spectra of launch][pol][N2][N1]
     long long jz0;            // spectrum index of Z[0]
-    const float2 *t4lo, *t4hi;
-    int q4;                   // W_N^m = t4lo[m & (2^q4-1)] * t4hi[m >> q4]
+    const float2 *tw4;        // [n1][k2] = W_N^(n1*k2), N entries
     // single-pass output
     float *part;              // [chunks of block][n_prod][N]
 };
@@ -69,14 +69,15 @@ struct BackArgs {
 
 struct ReduceArgs {
     const float *part;
-    float *carried;           // [n_prod][N], internal order u
+    const float *carried_in;  // [n_prod][N], internal order u: sum so far of the dump begun earlier
+    float *carried_out;       // [n_prod][N]: sum of the dump left incomplete by this block
     float *out;               // [dumps][n_prod][N], natural order k
     long long N, N1, N2;      // u = k2*N1 + k1  <->  k = k2 + N2*k1 (N2 == 1: identity)
     int n_prod;
     long long n_int, C;
     int G;
     long long j_lo, j_hi, gid_lo, gid_hi, d_lo;
-    int flush;                // 1: out[q][k] = carried (or 0 if !have_carried)
+    int flush;                // 1: out[q][k] = carried_in (or 0 if !have_carried)
     int have_carried;
 };
 
@@ -84,8 +85,8 @@ struct ReduceArgs {
 hipError_t launch_tables_taps(float *h, long long N, int P, int window, const double *d_custom,
                               hipStream_t s);
 hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s);
-hipError_t launch_tables_tw4(float2 *lo, float2 *hi, long long N, int q4, hipStream_t s);
-hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_chunks,
+hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_t s);
+hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_items,
                         hipStream_t s);
 hipError_t launch_back(const BackArgs &a, int npol, int n_chunks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s);

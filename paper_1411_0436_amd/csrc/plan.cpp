@@ -46,10 +46,11 @@ int ilog2(int64_t v) {
     return r;
 }
 
-Geo make_geo(int L) {
+// tp: complex points per polarisation per workgroup step of the kernel.
+Geo make_geo(int L, int tp = kTilePoints) {
     Geo g{};
     g.L = L;
-    g.T = kTilePoints / L;
+    g.T = tp / L;
     g.tw = nullptr;
     return g;
 }
@@ -87,11 +88,10 @@ struct pfbs_plan {
     int ntilesA, ntilesB;
     int G;
     int64_t C;
-    int q4;
     int64_t group_spectra;
     // device state
     float *taps;
-    float2 *twA, *twB, *t4lo, *t4hi;
+    float2 *twA, *twB, *tw4;
     uint8_t *hist[2];
     int hcur;
     int64_t frame_bytes;
@@ -99,11 +99,18 @@ struct pfbs_plan {
     size_t Zcap;      // float2 elements
     float *part;
     size_t partcap;   // floats
-    float *carried;
+    float *carried[2];   // ping-pong: read the current one, write the other
+    int ccur;
     int64_t device_bytes;
     // stream counters
     int64_t frames_seen, spectra_done, dumps_done;
     bool poisoned;
+    // optional kernel timing: (kind, start, stop) per launch since the last read
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    struct Rec { int kind; int i0; };
+    std::vector<Rec> recs;
+    size_t ev_used;
 };
 
 struct pfbs_batch {
@@ -127,11 +134,13 @@ pfbs_status hip_fail(pfbs_plan *p, hipError_t e, const char *what) {
 
 // Column length N2 (pass A) and row length N1 = N/N2 (pass B) of the
 // two-pass FFT: both must have kernels built for them and tile evenly.
+int back_tile(int64_t n1) { return n1 < 1024 ? 1024 : (int)n1; }  // row-pass points per pol
+
 bool split_ok(int64_t N, int64_t n2) {
     if (!is_pow2(n2) || n2 < 64 || n2 > 512) return false;
     const int64_t n1 = N / n2;
     if (n1 < 32 || n1 > kMaxSinglePass) return false;
-    return n1 % (kTilePoints / n2) == 0 && n2 % (kTilePoints / n1) == 0;
+    return n1 % (kTilePoints / n2) == 0 && n2 % (back_tile(n1) / n1) == 0;
 }
 
 pfbs_status validate_desc(const pfbs_plan_desc *d) {
@@ -199,10 +208,32 @@ hipError_t dalloc(pfbs_plan *p, T **ptr, size_t count) {
 }
 
 void free_plan_memory(pfbs_plan *p) {
-    void *bufs[] = {p->taps, p->twA, p->twB, p->t4lo, p->t4hi, p->hist[0], p->hist[1],
-                    p->Z, p->part, p->carried};
+    void *bufs[] = {p->taps, p->twA, p->twB, p->tw4, p->hist[0], p->hist[1],
+                    p->Z, p->part, p->carried[0], p->carried[1]};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+}
+
+// Run one launch, bracketed by timing events when the plan measures kernels.
+template <typename F>
+hipError_t timed(pfbs_plan *p, int kind, hipStream_t s, F &&launch) {
+    if (!p->timing) return launch();
+    while (p->ev_pool.size() < p->ev_used + 2) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        p->ev_pool.push_back(e);
+    }
+    const int i0 = (int)p->ev_used;
+    hipError_t r = hipEventRecord(p->ev_pool[i0], s);
+    if (r != hipSuccess) return r;
+    r = launch();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(p->ev_pool[i0 + 1], s);
+    if (r != hipSuccess) return r;
+    p->ev_used += 2;
+    p->recs.push_back({kind, i0});
+    return hipSuccess;
 }
 
 pfbs_status ensure_scratch(pfbs_plan *p, size_t z_elems, size_t part_floats) {
@@ -276,10 +307,13 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
     p->nprod = p->npol == 2 ? 4 : 1;
     p->fourstep = p->N > kMaxSinglePass;
     if (p->fourstep) {
-        p->N2 = desc->split_n2 ? desc->split_n2 : 256;
+        // Column length: 256 keeps the int8 rows of a column tile 64 bytes wide;
+        // from 2^18 channels 512 is used, whose shorter rows of the row pass
+        // measured the smaller worst-channel rounding error next to strong tones.
+        p->N2 = desc->split_n2 ? desc->split_n2 : (p->N >= (int64_t(1) << 18) ? 512 : 256);
         p->N1 = p->N / p->N2;
         p->gA = make_geo((int)p->N2);
-        p->gB = make_geo((int)p->N1);
+        p->gB = make_geo((int)p->N1, back_tile(p->N1));
         p->ntilesA = (int)(p->N1 / p->gA.T);
         p->ntilesB = (int)(p->N2 / p->gB.T);
     } else {
@@ -292,7 +326,6 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
     if (desc->chunk > 0) p->G = desc->chunk;
     else p->G = p->fourstep ? 16 : std::max(16, p->gA.T);
     p->C = (p->n_int + p->G - 1) / p->G;
-    p->q4 = (ilog2(p->N) + 1) / 2;
     const int64_t zbytes_per_spec = (int64_t)p->npol * p->N * (int64_t)sizeof(float2);
     const int64_t gb = desc->group_bytes > 0 ? desc->group_bytes : (int64_t(1) << 30);
     p->group_spectra = std::max<int64_t>(p->G, gb / zbytes_per_spec);
@@ -309,8 +342,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
         if (p->fourstep) {
             if ((e = dalloc(p, &p->twB, (size_t)tw16_count(p->gB))) != hipSuccess) break;
             p->gB.tw = p->twB;
-            if ((e = dalloc(p, &p->t4lo, (size_t)1 << p->q4)) != hipSuccess) break;
-            if ((e = dalloc(p, &p->t4hi, (size_t)(p->N >> p->q4))) != hipSuccess) break;
+            if ((e = dalloc(p, &p->tw4, (size_t)p->N)) != hipSuccess) break;
         }
         const size_t hbytes = (size_t)(p->P - 1) * p->frame_bytes;
         if (p->P > 1) {
@@ -318,8 +350,8 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
             if ((e = dalloc(p, &p->hist[1], hbytes)) != hipSuccess) break;
             if ((e = hipMemsetAsync(p->hist[0], 0, hbytes, s)) != hipSuccess) break;
         }
-        if ((e = dalloc(p, &p->carried, (size_t)p->nprod * p->N)) != hipSuccess) break;
-        if ((e = hipMemsetAsync(p->carried, 0, (size_t)p->nprod * p->N * sizeof(float), s)) != hipSuccess) break;
+        if ((e = dalloc(p, &p->carried[0], (size_t)p->nprod * p->N)) != hipSuccess) break;
+        if ((e = dalloc(p, &p->carried[1], (size_t)p->nprod * p->N)) != hipSuccess) break;
         int window = p->pfb ? p->window : PFBS_WINDOW_RECT;
         if (window == PFBS_WINDOW_CUSTOM) {
             const size_t n = (size_t)p->P * p->N;
@@ -330,7 +362,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
         if ((e = launch_tables_tw16(p->twA, p->gA.L, s)) != hipSuccess) break;
         if (p->fourstep) {
             if ((e = launch_tables_tw16(p->twB, p->gB.L, s)) != hipSuccess) break;
-            if ((e = launch_tables_tw4(p->t4lo, p->t4hi, p->N, p->q4, s)) != hipSuccess) break;
+            if ((e = launch_tables_tw4(p->tw4, p->N1, p->N2, s)) != hipSuccess) break;
         }
         if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     } while (0);
@@ -366,6 +398,7 @@ pfbs_status pfbs_plan_destroy(pfbs_plan *p) {
     if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     free_plan_memory(p);
     p->magic = kDead;
     delete p;
@@ -465,12 +498,10 @@ pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_
         fa.ntiles = p->ntilesA;
         fa.ch = ch;
         fa.Z = p->Z;
-        fa.t4lo = p->t4lo;
-        fa.t4hi = p->t4hi;
-        fa.q4 = p->q4;
+        fa.tw4 = p->tw4;
         fa.part = p->part;
         if (!p->fourstep) {
-            PFBS_HIP(p, launch_front(fa, p->npol, p->pfb, true, (int)n_chunks, s));
+            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(fa, p->npol, p->pfb, true, (int)n_chunks, s); }));
         } else {
             BackArgs ba;
             memset(&ba, 0, sizeof ba);
@@ -498,18 +529,26 @@ pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_
                 }
                 fa.ch.gid0 = g0;
                 fa.jz0 = gjs;
+                fa.sa0 = gjs;
+                fa.sa1 = gje;
+                // column pass: runs of ga spectra per workgroup, aiming at
+                // about 2048 workgroups per launch
+                const int64_t ns = gje - gjs;
+                fa.ga = (int)std::min<int64_t>(16, std::max<int64_t>(1, (p->ntilesA * ns) / 2048));
+                const int na = (int)((ns + fa.ga - 1) / fa.ga);
                 ba.ch.gid0 = g0;
                 ba.jz0 = gjs;
                 const int nc = (int)(g1 - g0 + 1);
-                PFBS_HIP(p, launch_front(fa, p->npol, p->pfb, false, nc, s));
-                PFBS_HIP(p, launch_back(ba, p->npol, nc, s));
+                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(fa, p->npol, p->pfb, false, na, s); }));
+                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(ba, p->npol, nc, s); }));
                 g0 = g1 + 1;
             }
         }
         ReduceArgs ra;
         memset(&ra, 0, sizeof ra);
         ra.part = p->part;
-        ra.carried = p->carried;
+        ra.carried_in = p->carried[p->ccur];
+        ra.carried_out = p->carried[p->ccur ^ 1];
         ra.out = d_dumps;
         ra.N = p->N;
         ra.N1 = p->N1;
@@ -524,10 +563,11 @@ pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_
         ra.gid_hi = gid_hi;
         ra.d_lo = j_lo / p->n_int;
         const int64_t d_hi = (j_hi - 1) / p->n_int;
-        PFBS_HIP(p, launch_reduce(ra, (int)(d_hi - ra.d_lo + 1), s));
+        PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(ra, (int)(d_hi - ra.d_lo + 1), s); }));
+        if ((d_hi + 1) * p->n_int > j_hi) p->ccur ^= 1;  // an incomplete dump went to carried_out
     }
     if (p->pfb && p->P > 1) {
-        PFBS_HIP(p, launch_history(p->hist[p->hcur ^ 1], fr, F, p->P - 1, p->frame_bytes, s));
+        PFBS_HIP(p, timed(p, 4, s, [&] { return launch_history(p->hist[p->hcur ^ 1], fr, F, p->P - 1, p->frame_bytes, s); }));
         p->hcur ^= 1;
     }
     p->frames_seen += F;
@@ -545,7 +585,7 @@ pfbs_status pfbs_flush(pfbs_plan *p, float *d_partial, int64_t *n_spectra, void 
     const int64_t cnt = p->spectra_done - p->dumps_done * p->n_int;
     ReduceArgs ra;
     memset(&ra, 0, sizeof ra);
-    ra.carried = p->carried;
+    ra.carried_in = p->carried[p->ccur];
     ra.out = d_partial;
     ra.N = p->N;
     ra.N1 = p->N1;
@@ -569,6 +609,7 @@ pfbs_status pfbs_plan_reset(pfbs_plan *p) {
     p->spectra_done = 0;
     p->dumps_done = 0;
     p->hcur = 0;
+    p->ccur = 0;
     p->poisoned = false;
     return PFBS_OK;
 }
@@ -592,6 +633,30 @@ pfbs_status pfbs_debug_pfb(pfbs_plan *p, const void *d_block, int64_t n, float *
     fr.hf0 = p->frames_seen - (p->P - 1);
     PFBS_HIP(p, launch_debug_pfb(d_y, fr, p->taps, p->N, p->P, p->npol, p->pfb, j_lo, j_hi,
                                  (hipStream_t)stream));
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_plan_timing(pfbs_plan *p, int32_t enable) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    p->timing = enable != 0;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_plan_timing_read(pfbs_plan *p, double *ms, int64_t *launches, int32_t n) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    if ((!ms || !launches) && n > 0) return fail(PFBS_ERR_INVALID, "NULL output arrays");
+    PFBS_HIP(p, hipSetDevice(p->device));
+    for (const auto &r : p->recs) {
+        PFBS_HIP(p, hipEventSynchronize(p->ev_pool[r.i0 + 1]));
+        float t = 0.f;
+        PFBS_HIP(p, hipEventElapsedTime(&t, p->ev_pool[r.i0], p->ev_pool[r.i0 + 1]));
+        if (r.kind < n) {
+            ms[r.kind] += t;
+            launches[r.kind] += 1;
+        }
+    }
+    p->recs.clear();
+    p->ev_used = 0;
     return PFBS_OK;
 }
 

@@ -24,8 +24,10 @@ EXPORTS = (
     "pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_dumps_in",
     "pfbs_execute", "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
     "pfbs_plan_get_info", "pfbs_last_error", "pfbs_batch_create", "pfbs_batch_execute",
-    "pfbs_batch_destroy", "pfbs_batch_plan",
+    "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
 )
+
+KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
 
 
 class PfbsError(RuntimeError):
@@ -83,11 +85,14 @@ def load(path: str = LIB_PATH):
     L.pfbs_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), i32]
     L.pfbs_batch_execute.argtypes = [vp, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64, pi64, i32, vp]
     L.pfbs_batch_destroy.argtypes = [vp]
+    L.pfbs_plan_timing.argtypes = [vp, i32]
+    L.pfbs_plan_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), pi64, i32]
     L.pfbs_batch_plan.argtypes = [vp, i32]
     L.pfbs_batch_plan.restype = vp
     for name in ("pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_execute",
                  "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
-                 "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy"):
+                 "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy",
+                 "pfbs_plan_timing", "pfbs_plan_timing_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -193,6 +198,17 @@ class Plan:
 
     def debug_taps(self, out, stream=None):
         _check(self._lib.pfbs_debug_taps(self._h, out.data_ptr(), _stream_ptr(stream)))
+
+    def timing(self, enable: bool = True):
+        _check(self._lib.pfbs_plan_timing(self._h, int(enable)))
+
+    def timing_read(self) -> dict:
+        """{kind: (total ms, launches)} since the last read (waits for the events)."""
+        n = len(KERNEL_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(self._lib.pfbs_plan_timing_read(self._h, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
     def info(self) -> dict:
         i = PlanInfo()

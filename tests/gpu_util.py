@@ -25,6 +25,34 @@ def rel_err(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
                      np.abs(got[2] - ref[2]) / sc, np.abs(got[3] - ref[3]) / sc])
 
 
+U32 = 2.0 ** -24
+
+
+def fp32_bound(ref: np.ndarray, N: int, c: float = 8.0) -> np.ndarray:
+    """Per-channel error bound of integrated products from FP32 arithmetic.
+
+    A floating-point FFT has a normwise error |dX_jk| <= c*u*sqrt(log2 N)*rms_j
+    (u = 2^-24, rms_j^2 = mean_k |X_jk|^2).  Summed over the spectra of a dump
+    and bounded with Cauchy-Schwarz this gives
+        |dD_k| <= 2 c u sqrt(log2 N) sqrt(D_k <D>)        (<D> = mean_k D_k),
+    plus the 1e-5 relative allowance of the integrated power itself.  For the
+    cross terms D_k is replaced by sqrt(XX_k YY_k).  The measured constant of
+    the FP32 path is about 2.4; c = 8 leaves margin."""
+    ref = np.asarray(ref, dtype=np.float64)
+    if ref.shape[0] == 1:
+        scale = ref[0][None]
+    else:
+        sc = np.sqrt(ref[0] * ref[1])
+        scale = np.stack([ref[0], ref[1], sc, sc])
+    mean = scale.mean(axis=1, keepdims=True)
+    return 1e-5 * scale + 2 * c * U32 * np.sqrt(np.log2(N)) * np.sqrt(scale * mean)
+
+
+def within_fp32_bound(got, ref, N) -> float:
+    """max over channels of |got - ref| / bound (<= 1 passes)."""
+    return float(np.max(np.abs(np.asarray(got, np.float64) - ref) / fp32_bound(ref, N)))
+
+
 def run_stream(plan, x: np.ndarray, block_frames, keep_device=False):
     """Feed x[T, n_pol, 2] in blocks of the given frame counts (cycled until
     the stream is used up; a short last block takes what is left).  Returns
