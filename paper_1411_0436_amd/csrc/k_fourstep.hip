@@ -23,9 +23,23 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArg
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
     const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
-    const int tile = blockIdx.x % a.ntiles;
+    // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+    // contiguous range of tiles and walk each tile's spectra consecutively, so
+    // the workgroups that share an L2 share taps and frames.
+    int tile, item;
+    {
+        const int nitems = gridDim.x / a.ntiles;
+        if ((a.ntiles & 7) == 0) {
+            const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+            tile = xcd * (a.ntiles >> 3) + local / nitems;
+            item = local % nitems;
+        } else {
+            tile = blockIdx.x % a.ntiles;
+            item = blockIdx.x / a.ntiles;
+        }
+    }
     // spectra [js, je): the item-th run of ga spectra of the launch's range
-    const long long js = a.sa0 + (long long)(blockIdx.x / a.ntiles) * a.ga;
+    const long long js = a.sa0 + (long long)item * a.ga;
     const long long je = min(js + (long long)a.ga, a.sa1);
     const long long N = a.N;
     const int N1 = (int)a.N1;
@@ -42,13 +56,13 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArg
 #pragma unroll
             for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
         for (int p = 0; p < P; ++p) {
-            const W *fb = frame_ptr<NPOL>(a.fr, j + p, N);
-            const float *hb = a.taps + (long long)p * N;
+            // uniform bases, 32-bit unsigned per-lane offsets
+            const W *fb = frame_ptr<NPOL>(a.fr, j + p, N) + n1_0;
+            const float *hb = a.taps + (long long)p * N + n1_0;
 #pragma unroll
             for (int s = 0; s < PTS; ++s) {
                 const int i = tid + NB * s;
-                const int c = i & (G::T - 1), n2 = i >> G::logT;
-                const int n = n1_0 + c + N1 * n2;
+                const unsigned n = (unsigned)((i & (G::T - 1)) + N1 * (i >> G::logT));
                 const W w = fb[n];
                 if (PFB) tap_fma<NPOL>(y[s], hb[n], w);
                 else Sample<NPOL>::unpack(w, y[s]);
@@ -79,7 +93,7 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArg
         }
         __syncthreads();
         // ---- coalesced store: T consecutive n1 of each (pol, k2) row
-        float2 *zb = a.Z + (j - a.jz0) * NPOL * N;
+        float2 *zb = a.Z + (j - a.jz0) * NPOL * N + n1_0;
 #pragma unroll
         for (int s = 0; s < (NPOL * kTilePoints) / NB; ++s) {
             const int i = tid + NB * s;
@@ -87,7 +101,7 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArg
             const int k2 = (i >> G::logT) & (L - 1);
             const int pp = i >> (G::logT + G::logL);
             const int ad = G::idx(pp, cc, k2);
-            zb[(long long)pp * N + (long long)k2 * N1 + n1_0 + cc] = make_float2(sre[ad], sim[ad]);
+            zb[(unsigned)(pp * (int)N + k2 * N1 + cc)] = make_float2(sre[ad], sim[ad]);
         }
         __syncthreads();
     }
@@ -122,14 +136,14 @@ __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a
         for (int q = 0; q < NP; ++q) acc[i][q] = 0.f;
 
     for (long long j = js; j < je; ++j) {
-        const float2 *zb = a.Z + (j - a.jz0) * NPOL * N;
+        const float2 *zb = a.Z + (j - a.jz0) * NPOL * N + (long long)k2_0 * L;
 #pragma unroll
         for (int s = 0; s < (NPOL * G::TP) / NB; ++s) {
             const int i = tid + NB * s;
             const int n1 = i & (L - 1);
             const int cc = (i >> G::logL) & (G::T - 1);
             const int pp = i >> (G::logL + G::logT);
-            const float2 z = zb[(long long)pp * N + (long long)(k2_0 + cc) * L + n1];
+            const float2 z = zb[(unsigned)(pp * (int)N + cc * L + n1)];
             const int ad = G::idx(pp, cc, n1);
             sre[ad] = z.x;
             sim[ad] = z.y;
