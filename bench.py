@@ -37,7 +37,7 @@ WORKLOADS = {
 }
 
 
-def _gen_block(args):
+def _gen_piece(args):
     name, t0, n = args
     from paper_1411_0436_amd import synth
     spec = {"c1": synth.spec_c1, "c2": synth.spec_c2, "c3": synth.spec_c3}[name]()
@@ -45,12 +45,20 @@ def _gen_block(args):
 
 
 def make_stream(w, procs):
-    jobs = [(w["spec"], b * w["block"], w["block"]) for b in range(w["blocks"])]
+    """The workload's blocks, generated in 2^22-sample pieces across processes
+    (the generator is per-window reproducible, so the pieces concatenate)."""
+    from paper_1411_0436_amd import synth
+    piece = max(synth.GEN_CHUNK, min(w["block"], 1 << 22))
+    total = w["blocks"] * w["block"]
+    jobs = [(w["spec"], t, min(piece, total - t)) for t in range(0, total, piece)]
     if procs > 1 and len(jobs) > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(min(procs, len(jobs))) as pool:
-            return pool.map(_gen_block, jobs)
-    return [_gen_block(j) for j in jobs]
+            parts = pool.map(_gen_piece, jobs)
+    else:
+        parts = [_gen_piece(j) for j in jobs]
+    x = np.concatenate(parts)
+    return [x[b * w["block"]:(b + 1) * w["block"]] for b in range(w["blocks"])]
 
 
 def flops_per_pol_sample(kind, w, N1, N2):
@@ -95,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--split-n2", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=0, help="override the workload's block count")
+    ap.add_argument("--group-mb", type=int, default=0, help="bound on the two-pass intermediate (MiB)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -118,7 +128,9 @@ def main():
     import torch
     from paper_1411_0436_amd import pfbspec as pf
 
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
+    if args.blocks:
+        w["blocks"] = args.blocks
     N, n_pol = w["N"], w["n_pol"]
     procs = min(16, len(os.sched_getaffinity(0)))
     t_gen = time.perf_counter()
@@ -126,7 +138,8 @@ def main():
     t_gen = time.perf_counter() - t_gen
     dev_blocks = [torch.from_numpy(b).cuda() for b in host_blocks]
     plan = pf.Plan(N, w["P"], mode=pf.MODE_DIRECT if w["direct"] else pf.MODE_PFB, n_pol=n_pol,
-                   n_int=w["n_int"], split_n2=args.split_n2, chunk=args.chunk)
+                   n_int=w["n_int"], split_n2=args.split_n2, chunk=args.chunk,
+                   group_bytes=args.group_mb << 20)
     info = plan.info()
     cap = max(plan.dumps_in(w["block"]) + 1, 2)
     dumps = torch.empty((cap, plan.n_prod, N), dtype=torch.float32, device="cuda")

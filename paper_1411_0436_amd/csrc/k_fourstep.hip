@@ -101,7 +101,15 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArg
             const int k2 = (i >> G::logT) & (L - 1);
             const int pp = i >> (G::logT + G::logL);
             const int ad = G::idx(pp, cc, k2);
-            zb[(unsigned)(pp * (int)N + k2 * N1 + cc)] = make_float2(sre[ad], sim[ad]);
+            float2 *zp = zb + (unsigned)(pp * (int)N + k2 * N1 + cc);
+            if (a.znt) {
+                // streaming store: Z is read once, by the row pass
+                float *zf = reinterpret_cast<float *>(zp);
+                __builtin_nontemporal_store(sre[ad], zf);
+                __builtin_nontemporal_store(sim[ad], zf + 1);
+            } else {
+                *zp = make_float2(sre[ad], sim[ad]);
+            }
         }
         __syncthreads();
     }
@@ -143,10 +151,17 @@ __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a
             const int n1 = i & (L - 1);
             const int cc = (i >> G::logL) & (G::T - 1);
             const int pp = i >> (G::logL + G::logT);
-            const float2 z = zb[(unsigned)(pp * (int)N + cc * L + n1)];
+            const float2 *zp = zb + (unsigned)(pp * (int)N + cc * L + n1);
             const int ad = G::idx(pp, cc, n1);
-            sre[ad] = z.x;
-            sim[ad] = z.y;
+            if (a.znt) {
+                const float *zf = reinterpret_cast<const float *>(zp);
+                sre[ad] = __builtin_nontemporal_load(zf);
+                sim[ad] = __builtin_nontemporal_load(zf + 1);
+            } else {
+                const float2 z = *zp;
+                sre[ad] = z.x;
+                sim[ad] = z.y;
+            }
         }
         __syncthreads();
         float2 v[16];

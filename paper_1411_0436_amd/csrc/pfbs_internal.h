@@ -50,6 +50,7 @@ struct FrontArgs {
     // pass A: spectra [sa0, sa1) in runs of ga per workgroup
     long long sa0, sa1;
     int ga;
+    int znt;                  // 1: streaming (non-temporal) stores of Z
     float2 *Z;                // [spectra of launch][pol][N2][N1]
     long long jz0;            // spectrum index of Z[0]
     const float2 *tw4;        // [n1][k2] = W_N^(n1*k2), N entries
@@ -59,6 +60,7 @@ struct FrontArgs {
 
 struct BackArgs {
     const float2 *Z;
+    int znt;                  // 1: streaming (non-temporal) loads of Z
     long long jz0;
     Geo g;                    // L = N1
     long long N, N1, N2;

@@ -89,6 +89,8 @@ struct pfbs_plan {
     int G;
     int64_t C;
     int64_t group_spectra;
+    int ga_force;        // column-pass spectra per workgroup (0 = automatic)
+    int znt;             // streaming stores/loads of the four-step intermediate
     // device state
     float *taps;
     float2 *twA, *twB, *tw4;
@@ -330,6 +332,9 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
     const int64_t gb = desc->group_bytes > 0 ? desc->group_bytes : (int64_t(1) << 30);
     p->group_spectra = std::max<int64_t>(p->G, gb / zbytes_per_spec);
     p->frame_bytes = p->N * 2 * p->npol;
+    // tuning overrides for measurement (also set by the autotuner)
+    if (const char *e = getenv("PFBS_GA")) p->ga_force = atoi(e);
+    if (const char *e = getenv("PFBS_ZNT")) p->znt = atoi(e);
 
     hipStream_t s = nullptr;
     double *d_custom = nullptr;
@@ -531,10 +536,14 @@ pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_
                 fa.jz0 = gjs;
                 fa.sa0 = gjs;
                 fa.sa1 = gje;
-                // column pass: runs of ga spectra per workgroup, aiming at
-                // about 2048 workgroups per launch
+                // column pass: runs of ga spectra per workgroup.  One spectrum
+                // per workgroup measured fastest (N = 2^15 and 2^19): the many
+                // workgroups of one column tile then run side by side on one
+                // XCD and share its taps and frames in L2.
                 const int64_t ns = gje - gjs;
-                fa.ga = (int)std::min<int64_t>(16, std::max<int64_t>(1, (p->ntilesA * ns) / 2048));
+                fa.ga = p->ga_force > 0 ? p->ga_force : 1;
+                fa.znt = p->znt;
+                ba.znt = p->znt;
                 const int na = (int)((ns + fa.ga - 1) / fa.ga);
                 ba.ch.gid0 = g0;
                 ba.jz0 = gjs;
