@@ -91,7 +91,14 @@ typedef enum {
  *   chunk       : spectra per partial integration (0 = automatic);
  *   split_n2    : column length of the two-pass FFT (0 = automatic);
  *   group_bytes : bound on the intermediate buffer of the two-pass FFT
- *                 (0 = automatic).                                           */
+ *                 (0 = automatic);
+ *   col_run     : spectra per workgroup of the column pass (0 = automatic);
+ *   stream_z    : 1 = streaming (non-temporal) stores and loads of the
+ *                 two-pass intermediate, 0 = ordinary ones.
+ * The last five only change speed, never results beyond FP32 rounding order.
+ * With tune = 1 they are taken from the autotune cache when it holds an
+ * entry for this device and shape (see pfbs_autotune); with tune = 2 a
+ * missing entry is measured first.                                          */
 typedef struct {
     int64_t N;
     int32_t P;
@@ -106,6 +113,8 @@ typedef struct {
     int32_t chunk;
     int64_t split_n2;
     int64_t group_bytes;
+    int32_t col_run;
+    int32_t stream_z;
 } pfbs_plan_desc;
 
 /* Create a plan (FP32 arithmetic; Section 4, initialisation: coefficients are
@@ -196,6 +205,21 @@ pfbs_status pfbs_plan_get_info(const pfbs_plan *plan, pfbs_plan_info *info);
 #define PFBS_KERNEL_KINDS 5
 pfbs_status pfbs_plan_timing(pfbs_plan *plan, int32_t enable);
 pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches, int32_t n);
+
+/* Autotuner.  Times candidate settings of the speed-only fields (split_n2,
+ * chunk, col_run, stream_z) for the plan shape in *desc on its device, each
+ * on the same synthetic device block of block_samples time samples (a
+ * positive multiple of N; 0 = 2^24), with HIP events around a few blocks, and
+ * writes the fastest into *best (a copy of *desc with those fields set and
+ * tune = 0) and its throughput in complex samples per second into
+ * *best_samples_per_s (may be NULL).  At most max_candidates settings are
+ * timed (0 = all).  If the environment variable PFBS_TUNE_CACHE names a file,
+ * the result is appended to it as one text line
+ *   pfbs-tune-v1 <arch> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z samples_per_s
+ * and later plans created with tune != 0 reuse the newest matching line.
+ * Synchronous; allocates device memory for the block and the trial plans.  */
+pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_samples, int32_t max_candidates,
+                          pfbs_plan_desc *best, double *best_samples_per_s);
 
 /* Human-readable detail of the calling thread's last failure ("" if none). */
 const char *pfbs_last_error(void);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfbspec.so")
-SOURCES = ["k_single.hip", "k_fourstep.hip", "k_aux.hip", "plan.cpp"]
+SOURCES = ["k_single.hip", "k_fourstep.hip", "k_batch.hip", "k_aux.hip", "plan.cpp", "autotune.cpp"]
 HEADERS = ["pfbs_internal.h", "fft_common.h", os.path.join("..", "..", "include", "pfbspec.h")]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -1,0 +1,331 @@
+// Kernel bodies as device functions of a virtual block id, so that the same
+// code serves a plan's own launches and the batched multi-sub-band launches.
+#pragma once
+
+#include "fft_common.h"
+
+namespace pfbs {
+
+// Single-pass spectrometer body for N <= 4096: unpack + polyphase
+// pre-filter + the whole N-point FFT + polarisation products + accumulation
+// (paper, Section 4: pre-filtering, parallel FFTs and accumulation of the
+// per-block loop).  A workgroup owns one chunk of consecutive spectra.  Each
+// step takes T = 4096/N consecutive spectra as the T columns of the batched
+// LDS FFT; a thread accumulates the products of fixed output bins of one
+// column in registers; at the end of the chunk the T columns are summed in
+// column order and written as the chunk's partial sum.
+template <int NPOL, bool PFB, int L>
+__device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
+    typedef Geom<L> G;
+    typedef typename Sample<NPOL>::word W;
+    constexpr int NB = G::TPP * NPOL;      // threads
+    constexpr int PTS = kTilePoints / NB;  // pre-filter points per thread (all pols each)
+    constexpr int NP = NPOL == 2 ? 4 : 1;  // products
+    constexpr int BINS = kTilePoints / NB; // accumulated bins per thread
+    extern __shared__ float smem[];
+    float *sre = smem;
+    float *sim = smem + NPOL * G::plane;
+    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
+    const long long gid = a.ch.gid0 + bid;
+    long long js, je;
+    chunk_range(a.ch, gid, js, je);
+    const int P = PFB ? a.P : 1;
+    // column and butterfly owned in the last radix-16 pass
+    const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+
+    float acc[BINS][NP];
+#pragma unroll
+    for (int i = 0; i < BINS; ++i)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) acc[i][q] = 0.f;
+
+    for (long long j0 = js; j0 < je; j0 += G::T) {
+        // ---- unpack + pre-filter (points along n: coalesced) into LDS
+        float2 y[PTS][NPOL];
+#pragma unroll
+        for (int s = 0; s < PTS; ++s)
+#pragma unroll
+            for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
+        for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int s = 0; s < PTS; ++s) {
+                const int i = tid + NB * s;
+                const int c = i >> G::logL, n = i & (L - 1);
+                const long long jj = j0 + c;
+                if (jj < je) {
+                    const W w = frame_ptr<NPOL>(a.fr, jj + p, L)[n];
+                    if (PFB) {
+                        tap_fma<NPOL>(y[s], a.taps[p * L + n], w);
+                    } else {
+                        Sample<NPOL>::unpack(w, y[s]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < PTS; ++s) {
+            const int i = tid + NB * s;
+            const int c = i >> G::logL, n = i & (L - 1);
+#pragma unroll
+            for (int pp = 0; pp < NPOL; ++pp) {
+                const int ad = G::idx(pp, c, n);
+                sre[ad] = y[s][pp].x;
+                sim[ad] = y[s][pp].y;
+            }
+        }
+        __syncthreads();
+        float2 v[16];
+        fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
+        if constexpr (NPOL == 2) {
+            // X and Y of a bin meet through LDS (natural order)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
+                sre[ad] = v[r].x;
+                sim[ad] = v[r].y;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < BINS; ++i) {
+                const int e = tid + NB * i;
+                const int c = e >> G::logL, k = e & (L - 1);
+                if (j0 + c < je) {
+                    const int ax = G::idx(0, c, k), ay = G::idx(1, c, k);
+                    prod4(acc[i], make_float2(sre[ax], sim[ax]), make_float2(sre[ay], sim[ay]));
+                }
+            }
+            __syncthreads();
+        } else {
+            if (j0 + c_own < je) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
+            }
+        }
+    }
+    // ---- sum the T columns in column order; write the chunk's partial
+    __syncthreads();
+    float *red = smem;  // [T][NP][L]
+    if constexpr (NPOL == 2) {
+#pragma unroll
+        for (int i = 0; i < BINS; ++i) {
+            const int e = tid + NB * i;
+            const int c = e >> G::logL, k = e & (L - 1);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) red[(c * NP + q) * L + k] = acc[i][q];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[c_own * L + bb_own + r * G::L16] = acc[r][0];
+    }
+    __syncthreads();
+    float *dst = a.part + (gid - a.ch.gid_lo) * (long long)NP * L;
+    for (int e = tid; e < NP * L; e += NB) {
+        float s = 0.f;
+#pragma unroll 4
+        for (int c = 0; c < G::T; ++c) s += red[c * NP * L + e];
+        dst[e] = s;
+    }
+}
+
+// Two-pass (four-step) bodies for 4096 < N <= 2^20.
+//
+// N = N1 * N2, n = n1 + N1*n2, k = k2 + N2*k1:
+//   X[k2 + N2 k1] = sum_n1 W_N1^(n1 k1) [ W_N^(n1 k2) sum_n2 y[n1 + N1 n2] W_N2^(n2 k2) ].
+// Column pass: unpack + pre-filter, the bracket for a tile of T = 4096/N2
+//   consecutive n1 (coalesced int8 rows), stored as Z[j][pol][k2][n1].
+// Row pass: for a tile of consecutive k2, the outer sum over n1 (contiguous
+//   rows of Z), the polarisation products and their accumulation in registers
+//   over the spectra of a chunk; the chunk's sums are written at
+//   u = k2*N1 + k1 (the reduction restores channel order).
+template <int NPOL, bool PFB, int L>
+__device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int nblk) {
+    typedef Geom<L> G;
+    typedef typename Sample<NPOL>::word W;
+    constexpr int NB = G::TPP * NPOL;
+    constexpr int PTS = kTilePoints / NB;
+    extern __shared__ float smem[];
+    float *sre = smem;
+    float *sim = smem + NPOL * G::plane;
+    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
+    // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+    // contiguous range of tiles and walk each tile's spectra consecutively, so
+    // the workgroups that share an L2 share taps and frames.
+    int tile, item;
+    {
+        const int nitems = nblk / a.ntiles;
+        if ((a.ntiles & 7) == 0) {
+            const int xcd = bid & 7, local = bid >> 3;
+            tile = xcd * (a.ntiles >> 3) + local / nitems;
+            item = local % nitems;
+        } else {
+            tile = bid % a.ntiles;
+            item = bid / a.ntiles;
+        }
+    }
+    // spectra [js, je): the item-th run of ga spectra of the launch's range
+    const long long js = a.sa0 + (long long)item * a.ga;
+    const long long je = min(js + (long long)a.ga, a.sa1);
+    const long long N = a.N;
+    const int N1 = (int)a.N1;
+    const int n1_0 = tile * G::T;
+    const int P = PFB ? a.P : 1;
+    const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+    // W_N^(n1 k2) of this thread's column, k2 = bb + r*L/16
+    const float2 *tw4 = a.tw4 + (unsigned)((n1_0 + c_own) * L + bb_own);
+
+    for (long long j = js; j < je; ++j) {
+        float2 y[PTS][NPOL];
+#pragma unroll
+        for (int s = 0; s < PTS; ++s)
+#pragma unroll
+            for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
+        for (int p = 0; p < P; ++p) {
+            // uniform bases, 32-bit unsigned per-lane offsets
+            const W *fb = frame_ptr<NPOL>(a.fr, j + p, N) + n1_0;
+            const float *hb = a.taps + (long long)p * N + n1_0;
+#pragma unroll
+            for (int s = 0; s < PTS; ++s) {
+                const int i = tid + NB * s;
+                const unsigned n = (unsigned)((i & (G::T - 1)) + N1 * (i >> G::logT));
+                const W w = fb[n];
+                if (PFB) tap_fma<NPOL>(y[s], hb[n], w);
+                else Sample<NPOL>::unpack(w, y[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < PTS; ++s) {
+            const int i = tid + NB * s;
+            const int c = i & (G::T - 1), n2 = i >> G::logT;
+#pragma unroll
+            for (int pp = 0; pp < NPOL; ++pp) {
+                const int ad = G::idx(pp, c, n2);
+                sre[ad] = y[s][pp].x;
+                sim[ad] = y[s][pp].y;
+            }
+        }
+        __syncthreads();
+        float2 v[16];
+        fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
+        // ---- twiddle W_N^(n1 k2), back to LDS in natural order
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int k2 = bb_own + r * G::L16;
+            const float2 z = cmul(v[r], tw4[r * G::L16]);
+            const int ad = G::idx(pol, c_own, k2);
+            sre[ad] = z.x;
+            sim[ad] = z.y;
+        }
+        __syncthreads();
+        // ---- coalesced store: T consecutive n1 of each (pol, k2) row
+        float2 *zb = a.Z + (j - a.jz0) * NPOL * N + n1_0;
+#pragma unroll
+        for (int s = 0; s < (NPOL * kTilePoints) / NB; ++s) {
+            const int i = tid + NB * s;
+            const int cc = i & (G::T - 1);
+            const int k2 = (i >> G::logT) & (L - 1);
+            const int pp = i >> (G::logT + G::logL);
+            const int ad = G::idx(pp, cc, k2);
+            float2 *zp = zb + (unsigned)(pp * (int)N + k2 * N1 + cc);
+            if (a.znt) {
+                // streaming store: Z is read once, by the row pass
+                float *zf = reinterpret_cast<float *>(zp);
+                __builtin_nontemporal_store(sre[ad], zf);
+                __builtin_nontemporal_store(sim[ad], zf + 1);
+            } else {
+                *zp = make_float2(sre[ad], sim[ad]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Row-pass tile: at least 1024 points per polarisation (64 threads each), so
+// short rows still give many small workgroups.
+template <int L> struct BackTile { static constexpr int TP = L < 1024 ? 1024 : L; };
+
+template <int NPOL, int L>
+__device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
+    typedef Geom<L, BackTile<L>::TP> G;
+    constexpr int NB = G::TPP * NPOL;
+    constexpr int NP = NPOL == 2 ? 4 : 1;
+    constexpr int BINS = G::TP / NB;
+    extern __shared__ float smem[];
+    float *sre = smem;
+    float *sim = smem + NPOL * G::plane;
+    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
+    const int tile = bid % a.ntiles;
+    const long long gid = a.ch.gid0 + bid / a.ntiles;
+    long long js, je;
+    chunk_range(a.ch, gid, js, je);
+    const long long N = a.N;
+    const int k2_0 = tile * G::T;
+    const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+
+    float acc[BINS][NP];
+#pragma unroll
+    for (int i = 0; i < BINS; ++i)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) acc[i][q] = 0.f;
+
+    for (long long j = js; j < je; ++j) {
+        const float2 *zb = a.Z + (j - a.jz0) * NPOL * N + (long long)k2_0 * L;
+#pragma unroll
+        for (int s = 0; s < (NPOL * G::TP) / NB; ++s) {
+            const int i = tid + NB * s;
+            const int n1 = i & (L - 1);
+            const int cc = (i >> G::logL) & (G::T - 1);
+            const int pp = i >> (G::logL + G::logT);
+            const float2 *zp = zb + (unsigned)(pp * (int)N + cc * L + n1);
+            const int ad = G::idx(pp, cc, n1);
+            if (a.znt) {
+                const float *zf = reinterpret_cast<const float *>(zp);
+                sre[ad] = __builtin_nontemporal_load(zf);
+                sim[ad] = __builtin_nontemporal_load(zf + 1);
+            } else {
+                const float2 z = *zp;
+                sre[ad] = z.x;
+                sim[ad] = z.y;
+            }
+        }
+        __syncthreads();
+        float2 v[16];
+        fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
+        if constexpr (NPOL == 2) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
+                sre[ad] = v[r].x;
+                sim[ad] = v[r].y;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < BINS; ++i) {
+                const int e = tid + NB * i;
+                const int c = e >> G::logL, k = e & (L - 1);
+                const int ax = G::idx(0, c, k), ay = G::idx(1, c, k);
+                prod4(acc[i], make_float2(sre[ax], sim[ax]), make_float2(sre[ay], sim[ay]));
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
+        }
+    }
+    float *dst = a.part + (gid - a.ch.gid_lo) * (long long)NP * N;
+    if constexpr (NPOL == 2) {
+#pragma unroll
+        for (int i = 0; i < BINS; ++i) {
+            const int e = tid + NB * i;
+            const int c = e >> G::logL, k1 = e & (L - 1);
+            const long long u = (long long)(k2_0 + c) * L + k1;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) dst[q * N + u] = acc[i][q];
+        }
+    } else {
+        const long long u0 = (long long)(k2_0 + c_own) * L + bb_own;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[u0 + r * G::L16] = acc[r][0];
+    }
+}
+
+}  // namespace pfbs

@@ -19,11 +19,11 @@ hipError_t init_fourstep(int lds_limit);
 // Four-step order (N2 > 1): a workgroup takes 8 k2 x 32 k1 (reads along k1,
 // one partial per thread), then writes channel order k = k2 + N2 k1 through
 // LDS.  Single pass (N2 == 1): 256 consecutive channels.
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+__device__ void reduce_body(const ReduceArgs &a, int bx, int by, int bz) {
     __shared__ float tile[8][33];
     const int t = threadIdx.x;
-    const long long d = a.d_lo + blockIdx.y;
-    const int q = blockIdx.z;
+    const long long d = a.d_lo + by;
+    const int q = bz;
     const long long g_first = max(a.gid_lo, d * a.C);
     const long long g_last = min(a.gid_hi, d * a.C + a.C - 1);
     const bool carried_in = a.flush ? (a.have_carried != 0) : (d * a.n_int < a.j_lo);
@@ -35,11 +35,11 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     long long k2b = 0, k1b = 0;
     if (tr) {
         const long long nt2 = a.N2 / 8;
-        k2b = (blockIdx.x % nt2) * 8;
-        k1b = (blockIdx.x / nt2) * 32;
+        k2b = (bx % nt2) * 8;
+        k1b = (bx / nt2) * 32;
         u = (k2b + (t >> 5)) * a.N1 + k1b + (t & 31);
     } else {
-        u = (long long)blockIdx.x * 256 + t;
+        u = (long long)bx * 256 + t;
     }
     float s = 0.f;
     if (u < N) {
@@ -72,15 +72,19 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+    reduce_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ------------------------------------------------------------ history -----
 
 // dst <- the last H frames of [history | block]; frames before the stream
 // start (never read) are written as zeros.
-__global__ __launch_bounds__(256) void k_history(uint4 *dst, Frames fr, long long F, int H,
-                                                 long long frame_vec) {
+__device__ void history_body(uint4 *dst, const Frames &fr, long long F, int H, long long frame_vec,
+                             int bid, int nblk) {
     const long long total = (long long)H * frame_vec;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = bid * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)nblk * blockDim.x) {
         const long long fp = i / frame_vec, off = i - fp * frame_vec;
         const long long gidx = fr.fs + F - H + fp;  // global frame index
         uint4 v = make_uint4(0, 0, 0, 0);
@@ -89,6 +93,28 @@ __global__ __launch_bounds__(256) void k_history(uint4 *dst, Frames fr, long lon
         else if (gidx >= fr.hf0 && gidx >= 0)
             v = reinterpret_cast<const uint4 *>(fr.hist)[(gidx - fr.hf0) * frame_vec + off];
         dst[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_history(uint4 *dst, Frames fr, long long F, int H,
+                                                 long long frame_vec) {
+    history_body(dst, fr, F, H, frame_vec, blockIdx.x, gridDim.x);
+}
+
+// Batched tail: dump reductions and tap-history copies of every sub-band.
+__global__ __launch_bounds__(256) void k_batch_tail(const BatchTailEntry *t, int n) {
+    if (n <= 0) return;
+    int e = 0;
+    while (e + 1 < n && (int)blockIdx.x >= t[e + 1].wg0) ++e;
+    const BatchTailEntry &E = t[e];
+    const int vb = blockIdx.x - E.wg0;
+    if (vb < 0 || vb >= E.wgn) return;
+    if (E.kind == 0) {
+        const int per_z = E.gx * E.gy;
+        const int bz = vb / per_z, rem = vb - bz * per_z;
+        reduce_body(E.r, rem % E.gx, rem / E.gx, bz);
+    } else {
+        history_body(reinterpret_cast<uint4 *>(E.hdst), E.fr, E.F, E.H, E.frame_vec, vb, E.wgn);
     }
 }
 
@@ -178,7 +204,31 @@ __global__ void k_tw4(float2 *tw4, long long N1, long long N2) {
     }
 }
 
+// Synthetic int8 words for the autotuner: each byte a hashed function of its
+// index (finaliser of MurmurHash3), folded to roughly Gaussian-sized values.
+__global__ void k_synth(uint32_t *w, long long n, uint32_t seed) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        uint32_t x = (uint32_t)i * 0x9E3779B9u ^ seed;
+        x ^= x >> 16; x *= 0x85EBCA6Bu; x ^= x >> 13; x *= 0xC2B2AE35u; x ^= x >> 16;
+        // each byte: sum of two 5-bit fields minus 31 -> [-31, 31], triangular
+        uint32_t o = 0;
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t y = (x >> (8 * b)) * 0x2545F491u;
+            const int v = (int)((y >> 5) & 31) + (int)((y >> 11) & 31) - 31;
+            o |= (uint32_t)(uint8_t)(int8_t)v << (8 * b);
+        }
+        w[i] = o;
+    }
+}
+
 // ----------------------------------------------------------- launchers ----
+
+hipError_t launch_synth(uint32_t *words, long long n_words, uint32_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_synth, dim3(1024), dim3(256), 0, s, words, n_words, seed);
+    return hipGetLastError();
+}
+
 
 static int grid_for(long long n, int per_block) {
     long long b = (n + per_block - 1) / per_block;
@@ -246,11 +296,21 @@ hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long 
     return hipGetLastError();
 }
 
+hipError_t launch_batch_tail(const BatchTailEntry *t, int n, int total_wg, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_tail, dim3(total_wg > 0 ? total_wg : 1), dim3(256), 0, s, t, n);
+    return hipGetLastError();
+}
+
+const void *batch_tail_fn() { return reinterpret_cast<const void *>(&k_batch_tail); }
+
+hipError_t init_batch(int lds_limit);
+
 hipError_t kernels_init() {
     const int lim = 96 * 1024;  // largest workgroup LDS is ~74 KB
     hipError_t e = init_single(lim);
     hipError_t e2 = init_fourstep(lim);
-    return e != hipSuccess ? e : e2;
+    hipError_t e3 = init_batch(lim);
+    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);
 }
 
 }  // namespace pfbs

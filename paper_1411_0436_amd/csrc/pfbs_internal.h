@@ -83,6 +83,59 @@ struct ReduceArgs {
     int have_carried;
 };
 
+// ---- batched launches: one dispatcher kernel per phase serves every
+// sub-band of a batch; each workgroup finds its entry by its block id.
+constexpr int kMaxBatch = 64;
+
+struct BatchFrontEntry {
+    int kind;        // 0 = single pass, 1 = column pass
+    int pfb;
+    int L;
+    int wg0, wgn;    // the entry's virtual block ids are [wg0, wg0 + wgn)
+    FrontArgs a;
+};
+
+struct BatchBackEntry {
+    int L;
+    int wg0, wgn;
+    BackArgs a;
+};
+
+struct BatchTailEntry {
+    int kind;        // 0 = dump reduction, 1 = tap history
+    int wg0, wgn;
+    int gx, gy;      // reduction grid x, y (z = products)
+    ReduceArgs r;
+    uint8_t *hdst;   // history
+    Frames fr;
+    long long F, frame_vec;
+    int H;
+};
+
+hipError_t launch_batch_front(const BatchFrontEntry *t, int n, int total_wg, int npol, size_t lds,
+                              hipStream_t s);
+hipError_t launch_batch_back(const BatchBackEntry *t, int n, int total_wg, int npol, int threads,
+                             size_t lds, hipStream_t s);
+hipError_t launch_batch_tail(const BatchTailEntry *t, int n, int total_wg, hipStream_t s);
+// Kernel symbol and block size of a batched launch, for HIP graph node updates.
+const void *batch_front_fn(int npol);
+const void *batch_back_fn(int npol, int threads);
+const void *batch_tail_fn();
+size_t back_lds_bytes_for(int L, int npol);
+
+}  // namespace pfbs
+
+#include "../../include/pfbspec.h"
+
+namespace pfbs {
+
+// ---- autotune cache (autotune.cpp) ----
+// Fill *out from the newest cache line matching desc's shape on the current
+// device (speed-only fields); with measure_if_missing, run the autotuner when
+// there is none.  Leaves *out = *desc when nothing applies.
+pfbs_status tune_lookup(const pfbs_plan_desc *desc, bool measure_if_missing, pfbs_plan_desc *out);
+hipError_t launch_synth(uint32_t *words, long long n_words, uint32_t seed, hipStream_t s);
+
 // ---- launchers (kernels.hip) ----
 hipError_t launch_tables_taps(float *h, long long N, int P, int window, const double *d_custom,
                               hipStream_t s);

@@ -9,9 +9,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -118,6 +120,24 @@ struct pfbs_plan {
 struct pfbs_batch {
     uint32_t magic;
     std::vector<pfbs_plan *> plans;
+    int npol;
+    std::vector<int> back_threads;   // row-pass workgroup sizes present (fixed launch list)
+    // entry tables: device copy read by the dispatchers, two pinned staging copies
+    struct Tables {
+        BatchFrontEntry front[kMaxBatch];
+        BatchBackEntry back[kMaxBatch];
+        BatchTailEntry tail[2 * kMaxBatch];
+    };
+    Tables *d_tab;
+    Tables *h_tab[2];
+    hipEvent_t staged[2];
+    int stage;
+    // HIP graph of the launch sequence, captured on first use
+    hipStream_t gstream;
+    hipEvent_t ev_in, ev_out;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    std::vector<hipGraphNode_t> gnodes;   // in launch-list order
 };
 
 namespace {
@@ -173,6 +193,9 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
                         "row length 32..4096)", (long long)d->split_n2, (long long)d->N);
     }
     if (d->group_bytes < 0) return fail(PFBS_ERR_INVALID, "group_bytes < 0");
+    if (d->col_run < 0 || d->col_run > 64) return fail(PFBS_ERR_INVALID, "col_run=%d out of [0, 64]", d->col_run);
+    if (d->stream_z != 0 && d->stream_z != 1) return fail(PFBS_ERR_INVALID, "stream_z must be 0 or 1");
+    if (d->tune < 0 || d->tune > 2) return fail(PFBS_ERR_INVALID, "tune must be 0, 1 or 2");
     return PFBS_OK;
 }
 
@@ -268,11 +291,19 @@ extern "C" {
 
 const char *pfbs_last_error(void) { return g_err.c_str(); }
 
-pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
+pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) {
     if (!out) return fail(PFBS_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    pfbs_status st = validate_desc(desc);
+    pfbs_status st = validate_desc(desc_in);
     if (st != PFBS_OK) return st;
+    pfbs_plan_desc tuned = *desc_in;
+    if (desc_in->tune != 0) {
+        st = pfbs::tune_lookup(desc_in, desc_in->tune == 2, &tuned);
+        if (st != PFBS_OK) return st;
+        st = validate_desc(&tuned);
+        if (st != PFBS_OK) return st;
+    }
+    const pfbs_plan_desc *desc = &tuned;
     if (desc->precision != PFBS_PREC_FP32)
         return fail(PFBS_ERR_UNSUPPORTED, "precision %d is not available in this build", desc->precision);
 
@@ -332,7 +363,9 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc) {
     const int64_t gb = desc->group_bytes > 0 ? desc->group_bytes : (int64_t(1) << 30);
     p->group_spectra = std::max<int64_t>(p->G, gb / zbytes_per_spec);
     p->frame_bytes = p->N * 2 * p->npol;
-    // tuning overrides for measurement (also set by the autotuner)
+    p->ga_force = desc->col_run;
+    p->znt = desc->stream_z;
+    // environment overrides, for measurement sweeps
     if (const char *e = getenv("PFBS_GA")) p->ga_force = atoi(e);
     if (const char *e = getenv("PFBS_ZNT")) p->znt = atoi(e);
 
@@ -449,140 +482,207 @@ static pfbs_status check_block(const pfbs_plan *p, const void *d_block, int64_t 
     return PFBS_OK;
 }
 
-pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps, int64_t cap,
-                         int64_t *n_written, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// One block's work for one plan, computed on the host before any launch.
+struct Group {
+    FrontArgs fa;
+    BackArgs ba;
+    int na;   // column-pass items (runs of ga spectra)
+    int nc;   // chunks
+};
+
+struct Prepared {
+    int64_t F = 0, j_lo = 0, j_hi = 0, nd_out = 0;
+    bool any = false;
+    FrontArgs single{};
+    int single_chunks = 0;
+    std::vector<Group> groups;
+    ReduceArgs ra{};
+    int n_dumps = 0;
+    bool hist = false;
+    Frames fr{};
+    bool flip_carried = false;
+};
+
+// Validate the block, size the scratch buffers and compute every launch's
+// arguments.  Changes no stream state.  one_group: the whole block's
+// intermediate in one column pass / row pass pair (batched launches).
+pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps, int64_t cap,
+                    bool one_group, Prepared &w) {
     pfbs_status st = check_block(p, d_block, n);
     if (st != PFBS_OK) return st;
-    if (!n_written) return fail(PFBS_ERR_INVALID, "n_dumps_written is NULL");
-    const int64_t F = n / p->N;
-    int64_t j_lo, j_hi;
-    block_spectra(p, F, j_lo, j_hi);
-    const int64_t nd_out = j_hi / p->n_int - j_lo / p->n_int;
-    if (nd_out > 0 && !d_dumps) return fail(PFBS_ERR_INVALID, "d_dumps is NULL but %lld dumps complete", (long long)nd_out);
-    if (cap < nd_out)
+    w.F = n / p->N;
+    block_spectra(p, w.F, w.j_lo, w.j_hi);
+    w.nd_out = w.j_hi / p->n_int - w.j_lo / p->n_int;
+    if (w.nd_out > 0 && !d_dumps)
+        return fail(PFBS_ERR_INVALID, "d_dumps is NULL but %lld dumps complete", (long long)w.nd_out);
+    if (cap < w.nd_out)
         return fail(PFBS_ERR_INVALID, "dump_capacity=%lld < %lld dumps completed by this block",
-                    (long long)cap, (long long)nd_out);
-    *n_written = 0;
-    hipStream_t s = (hipStream_t)stream;
+                    (long long)cap, (long long)w.nd_out);
     PFBS_HIP(p, hipSetDevice(p->device));
+    w.fr.blk = (const uint8_t *)d_block;
+    w.fr.hist = p->hist[p->hcur];
+    w.fr.fs = p->frames_seen;
+    w.fr.hf0 = p->frames_seen - (p->P - 1);
+    w.hist = p->pfb && p->P > 1;
+    w.any = w.j_hi > w.j_lo;
+    w.groups.clear();
+    if (!w.any) return PFBS_OK;
+    const int64_t j_lo = w.j_lo, j_hi = w.j_hi;
+    const int64_t gid_lo = chunk_of(p, j_lo), gid_hi = chunk_of(p, j_hi - 1);
+    const int64_t n_chunks = gid_hi - gid_lo + 1;
+    Chunks ch;
+    ch.n_int = p->n_int;
+    ch.C = p->C;
+    ch.G = p->G;
+    ch.j_lo = j_lo;
+    ch.j_hi = j_hi;
+    ch.gid_lo = gid_lo;
+    ch.gid0 = gid_lo;
+    size_t zneed = 0;
+    if (p->fourstep) {
+        const int64_t gs = one_group ? (j_hi - j_lo + p->G)
+                                     : std::min<int64_t>(p->group_spectra, j_hi - j_lo + p->G);
+        zneed = (size_t)(gs + p->G) * p->npol * p->N;
+    }
+    st = ensure_scratch(p, zneed, (size_t)n_chunks * p->nprod * p->N);
+    if (st != PFBS_OK) return st;
 
-    Frames fr;
-    fr.blk = (const uint8_t *)d_block;
-    fr.hist = p->hist[p->hcur];
-    fr.fs = p->frames_seen;
-    fr.hf0 = p->frames_seen - (p->P - 1);
-
-    if (j_hi > j_lo) {
-        const int64_t gid_lo = chunk_of(p, j_lo), gid_hi = chunk_of(p, j_hi - 1);
-        const int64_t n_chunks = gid_hi - gid_lo + 1;
-        Chunks ch;
-        ch.n_int = p->n_int;
-        ch.C = p->C;
-        ch.G = p->G;
-        ch.j_lo = j_lo;
-        ch.j_hi = j_hi;
-        ch.gid_lo = gid_lo;
-        ch.gid0 = gid_lo;
-        size_t zneed = 0;
-        if (p->fourstep) {
-            const int64_t gs = std::min<int64_t>(p->group_spectra, j_hi - j_lo + p->G);
-            zneed = (size_t)(gs + p->G) * p->npol * p->N;
+    FrontArgs fa;
+    memset(&fa, 0, sizeof fa);
+    fa.fr = w.fr;
+    fa.taps = p->taps;
+    fa.g = p->gA;
+    fa.N = p->N;
+    fa.N1 = p->N1;
+    fa.N2 = p->N2;
+    fa.P = p->P;
+    fa.ntiles = p->ntilesA;
+    fa.ch = ch;
+    fa.Z = p->Z;
+    fa.tw4 = p->tw4;
+    fa.part = p->part;
+    if (!p->fourstep) {
+        w.single = fa;
+        w.single_chunks = (int)n_chunks;
+    } else {
+        BackArgs ba;
+        memset(&ba, 0, sizeof ba);
+        ba.Z = p->Z;
+        ba.g = p->gB;
+        ba.N = p->N;
+        ba.N1 = p->N1;
+        ba.N2 = p->N2;
+        ba.ntiles = p->ntilesB;
+        ba.ch = ch;
+        ba.part = p->part;
+        // groups of whole chunks whose intermediate fits the Z buffer
+        const int64_t zlimit =
+            one_group ? (j_hi - j_lo + p->G)
+                      : std::min<int64_t>((int64_t)(p->Zcap / ((size_t)p->npol * p->N)),
+                                          std::max<int64_t>(p->group_spectra, p->G));
+        int64_t g0 = gid_lo;
+        while (g0 <= gid_hi) {
+            int64_t gjs, gje, tjs, tje;
+            chunk_span(p, g0, j_lo, j_hi, gjs, gje);
+            int64_t g1 = g0;
+            while (g1 + 1 <= gid_hi) {
+                chunk_span(p, g1 + 1, j_lo, j_hi, tjs, tje);
+                if (tje - gjs > zlimit) break;
+                ++g1;
+                gje = tje;
+            }
+            Group g;
+            g.fa = fa;
+            g.ba = ba;
+            g.fa.ch.gid0 = g0;
+            g.fa.jz0 = gjs;
+            g.fa.sa0 = gjs;
+            g.fa.sa1 = gje;
+            // column pass: runs of ga spectra per workgroup.  One spectrum
+            // per workgroup measured fastest (N = 2^15 and 2^19): the many
+            // workgroups of one column tile then run side by side on one
+            // XCD and share its taps and frames in L2.
+            const int64_t ns = gje - gjs;
+            g.fa.ga = p->ga_force > 0 ? p->ga_force : 1;
+            g.fa.znt = p->znt;
+            g.ba.znt = p->znt;
+            g.na = (int)((ns + g.fa.ga - 1) / g.fa.ga);
+            g.ba.ch.gid0 = g0;
+            g.ba.jz0 = gjs;
+            g.nc = (int)(g1 - g0 + 1);
+            w.groups.push_back(g);
+            g0 = g1 + 1;
         }
-        st = ensure_scratch(p, zneed, (size_t)n_chunks * p->nprod * p->N);
-        if (st != PFBS_OK) return st;
+    }
+    ReduceArgs &ra = w.ra;
+    memset(&ra, 0, sizeof ra);
+    ra.part = p->part;
+    ra.carried_in = p->carried[p->ccur];
+    ra.carried_out = p->carried[p->ccur ^ 1];
+    ra.out = d_dumps;
+    ra.N = p->N;
+    ra.N1 = p->N1;
+    ra.N2 = p->fourstep ? p->N2 : 1;
+    ra.n_prod = p->nprod;
+    ra.n_int = p->n_int;
+    ra.C = p->C;
+    ra.G = p->G;
+    ra.j_lo = j_lo;
+    ra.j_hi = j_hi;
+    ra.gid_lo = gid_lo;
+    ra.gid_hi = gid_hi;
+    ra.d_lo = j_lo / p->n_int;
+    const int64_t d_hi = (j_hi - 1) / p->n_int;
+    w.n_dumps = (int)(d_hi - ra.d_lo + 1);
+    w.flip_carried = (d_hi + 1) * p->n_int > j_hi;  // an incomplete dump goes to carried_out
+    return PFBS_OK;
+}
 
-        FrontArgs fa;
-        memset(&fa, 0, sizeof fa);
-        fa.fr = fr;
-        fa.taps = p->taps;
-        fa.g = p->gA;
-        fa.N = p->N;
-        fa.N1 = p->N1;
-        fa.N2 = p->N2;
-        fa.P = p->P;
-        fa.ntiles = p->ntilesA;
-        fa.ch = ch;
-        fa.Z = p->Z;
-        fa.tw4 = p->tw4;
-        fa.part = p->part;
+pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s) {
+    if (w.any) {
         if (!p->fourstep) {
-            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(fa, p->npol, p->pfb, true, (int)n_chunks, s); }));
+            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(w.single, p->npol, p->pfb, true, w.single_chunks, s); }));
         } else {
-            BackArgs ba;
-            memset(&ba, 0, sizeof ba);
-            ba.Z = p->Z;
-            ba.g = p->gB;
-            ba.N = p->N;
-            ba.N1 = p->N1;
-            ba.N2 = p->N2;
-            ba.ntiles = p->ntilesB;
-            ba.ch = ch;
-            ba.part = p->part;
-            // groups of whole chunks whose intermediate fits the Z buffer
-            const int64_t zlimit = std::min<int64_t>(
-                (int64_t)(p->Zcap / ((size_t)p->npol * p->N)), std::max<int64_t>(p->group_spectra, p->G));
-            int64_t g0 = gid_lo;
-            while (g0 <= gid_hi) {
-                int64_t gjs, gje, tjs, tje;
-                chunk_span(p, g0, j_lo, j_hi, gjs, gje);
-                int64_t g1 = g0;
-                while (g1 + 1 <= gid_hi) {
-                    chunk_span(p, g1 + 1, j_lo, j_hi, tjs, tje);
-                    if (tje - gjs > zlimit) break;
-                    ++g1;
-                    gje = tje;
-                }
-                fa.ch.gid0 = g0;
-                fa.jz0 = gjs;
-                fa.sa0 = gjs;
-                fa.sa1 = gje;
-                // column pass: runs of ga spectra per workgroup.  One spectrum
-                // per workgroup measured fastest (N = 2^15 and 2^19): the many
-                // workgroups of one column tile then run side by side on one
-                // XCD and share its taps and frames in L2.
-                const int64_t ns = gje - gjs;
-                fa.ga = p->ga_force > 0 ? p->ga_force : 1;
-                fa.znt = p->znt;
-                ba.znt = p->znt;
-                const int na = (int)((ns + fa.ga - 1) / fa.ga);
-                ba.ch.gid0 = g0;
-                ba.jz0 = gjs;
-                const int nc = (int)(g1 - g0 + 1);
-                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(fa, p->npol, p->pfb, false, na, s); }));
-                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(ba, p->npol, nc, s); }));
-                g0 = g1 + 1;
+            for (const Group &g : w.groups) {
+                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(g.fa, p->npol, p->pfb, false, g.na, s); }));
+                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(g.ba, p->npol, g.nc, s); }));
             }
         }
-        ReduceArgs ra;
-        memset(&ra, 0, sizeof ra);
-        ra.part = p->part;
-        ra.carried_in = p->carried[p->ccur];
-        ra.carried_out = p->carried[p->ccur ^ 1];
-        ra.out = d_dumps;
-        ra.N = p->N;
-        ra.N1 = p->N1;
-        ra.N2 = p->fourstep ? p->N2 : 1;
-        ra.n_prod = p->nprod;
-        ra.n_int = p->n_int;
-        ra.C = p->C;
-        ra.G = p->G;
-        ra.j_lo = j_lo;
-        ra.j_hi = j_hi;
-        ra.gid_lo = gid_lo;
-        ra.gid_hi = gid_hi;
-        ra.d_lo = j_lo / p->n_int;
-        const int64_t d_hi = (j_hi - 1) / p->n_int;
-        PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(ra, (int)(d_hi - ra.d_lo + 1), s); }));
-        if ((d_hi + 1) * p->n_int > j_hi) p->ccur ^= 1;  // an incomplete dump went to carried_out
+        PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(w.ra, w.n_dumps, s); }));
     }
-    if (p->pfb && p->P > 1) {
-        PFBS_HIP(p, timed(p, 4, s, [&] { return launch_history(p->hist[p->hcur ^ 1], fr, F, p->P - 1, p->frame_bytes, s); }));
-        p->hcur ^= 1;
+    if (w.hist) {
+        PFBS_HIP(p, timed(p, 4, s, [&] { return launch_history(p->hist[p->hcur ^ 1], w.fr, w.F, p->P - 1, p->frame_bytes, s); }));
     }
-    p->frames_seen += F;
-    p->spectra_done = j_hi;
-    p->dumps_done += nd_out;
-    *n_written = nd_out;
+    return PFBS_OK;
+}
+
+void commit(pfbs_plan *p, const Prepared &w) {
+    if (w.any && w.flip_carried) p->ccur ^= 1;
+    if (w.hist) p->hcur ^= 1;
+    p->frames_seen += w.F;
+    p->spectra_done = w.j_hi;
+    p->dumps_done += w.nd_out;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps, int64_t cap,
+                         int64_t *n_written, void *stream) {
+    if (!n_written) return fail(PFBS_ERR_INVALID, "n_dumps_written is NULL");
+    Prepared w;
+    pfbs_status st = prepare(p, d_block, n, d_dumps, cap, false, w);
+    if (st != PFBS_OK) return st;
+    *n_written = 0;
+    st = launch_prepared(p, w, (hipStream_t)stream);
+    if (st != PFBS_OK) return st;
+    commit(p, w);
+    *n_written = w.nd_out;
     return PFBS_OK;
 }
 
@@ -680,28 +780,91 @@ pfbs_status pfbs_debug_taps(pfbs_plan *p, float *d_out, void *stream) {
 
 // ---------------------------------------------------------------- batch ----
 
+}  // extern "C"
+
+namespace {
+
+void batch_free(pfbs_batch *b) {
+    for (pfbs_plan *p : b->plans) pfbs_plan_destroy(p);
+    b->plans.clear();
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    for (int k = 0; k < 2; ++k) {
+        if (b->staged[k]) (void)hipEventDestroy(b->staged[k]);
+        if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+    }
+    if (b->d_tab) (void)hipFree(b->d_tab);
+}
+
+int row_threads(const pfbs_plan *p) { return back_tile(p->N1) / 16 * p->npol; }
+
+// One kernel launch of a batched block: which dispatcher, its grid, LDS and
+// entry table.
+struct BLaunch {
+    const void *fn;
+    int grid, threads;
+    size_t lds;
+    const void *table;
+    int n;
+};
+
+}  // namespace
+
+extern "C" {
+
 pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int32_t n) {
     if (!out) return fail(PFBS_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (!descs || n < 1 || n > 64) return fail(PFBS_ERR_INVALID, "need 1..64 descriptions");
+    if (!descs || n < 1 || n > kMaxBatch) return fail(PFBS_ERR_INVALID, "need 1..%d descriptions", kMaxBatch);
     for (int i = 0; i < n; ++i) {
         pfbs_status st = validate_desc(&descs[i]);
         if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
         if (descs[i].n_pol != descs[0].n_pol) return fail(PFBS_ERR_INVALID, "all sub-bands need the same n_pol");
+        if (descs[i].precision != PFBS_PREC_FP32)
+            return fail(PFBS_ERR_UNSUPPORTED, "sub-band %d: batched launches run the FP32 path", i);
     }
     pfbs_batch *b = new (std::nothrow) pfbs_batch();
     if (!b) return fail(PFBS_ERR_NOMEM, "host allocation");
     b->magic = kMagic;
-    for (int i = 0; i < n; ++i) {
+    b->npol = descs[0].n_pol;
+    pfbs_status st = PFBS_OK;
+    for (int i = 0; i < n && st == PFBS_OK; ++i) {
         pfbs_plan *p = nullptr;
-        pfbs_status st = pfbs_plan_create_ex(&p, &descs[i]);
+        st = pfbs_plan_create_ex(&p, &descs[i]);
         if (st != PFBS_OK) {
             std::string why = g_err;
-            for (pfbs_plan *q : b->plans) pfbs_plan_destroy(q);
-            delete b;
-            return fail(st, "sub-band %d: %s", i, why.c_str());
+            st = fail(st, "sub-band %d: %s", i, why.c_str());
+            break;
         }
         b->plans.push_back(p);
+        if (p->fourstep) {
+            const int t = row_threads(p);
+            if (std::find(b->back_threads.begin(), b->back_threads.end(), t) == b->back_threads.end())
+                b->back_threads.push_back(t);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (st == PFBS_OK) {
+        std::sort(b->back_threads.begin(), b->back_threads.end());
+        if ((e = hipMalloc((void **)&b->d_tab, sizeof(pfbs_batch::Tables))) == hipSuccess &&
+            (e = hipHostMalloc((void **)&b->h_tab[0], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
+            (e = hipHostMalloc((void **)&b->h_tab[1], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&b->staged[0], hipEventDisableTiming)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&b->staged[1], hipEventDisableTiming)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) == hipSuccess) {
+            // default-priority stream for graph replays, joined to the caller's by events
+            e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+        }
+        if (e != hipSuccess) st = hip_fail(nullptr, e, "batch resources");
+    }
+    if (st != PFBS_OK) {
+        batch_free(b);
+        delete b;
+        return st;
     }
     *out = b;
     return PFBS_OK;
@@ -712,19 +875,175 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
                                int32_t use_graph, void *stream) {
     if (!b || b->magic != kMagic) return fail(PFBS_ERR_STATE, "not a live batch");
     if (!d_blocks || !n_samples || !d_dumps || !caps || !n_dumps) return fail(PFBS_ERR_INVALID, "NULL argument");
-    (void)use_graph;
     const int n = (int)b->plans.size();
+    std::vector<Prepared> w(n);
     for (int i = 0; i < n; ++i) {
-        pfbs_status st = check_block(b->plans[i], d_blocks[i], n_samples[i]);
+        pfbs_status st = prepare(b->plans[i], d_blocks[i], n_samples[i], d_dumps[i], caps[i], true, w[i]);
         if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
-        const int64_t nd = pfbs_dumps_in(b->plans[i], n_samples[i]);
-        if (caps[i] < nd || (nd > 0 && !d_dumps[i]))
-            return fail(PFBS_ERR_INVALID, "sub-band %d: dump capacity %lld < %lld", i, (long long)caps[i], (long long)nd);
+    }
+    // ---- entry tables (host staging buffer k; wait until its last upload is done)
+    const int k = b->stage;
+    hipError_t e = hipEventSynchronize(b->staged[k]);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "batch staging");
+    pfbs_batch::Tables &T = *b->h_tab[k];
+    int nf = 0, ntl = 0, wf = 0, wt = 0;
+    size_t lds_front = 0;
+    std::vector<int> nb(b->back_threads.size(), 0), wb(b->back_threads.size(), 0);
+    std::vector<size_t> lds_back(b->back_threads.size(), 0);
+    // back entries of each workgroup size are stored contiguously per size
+    std::vector<std::vector<BatchBackEntry>> backs(b->back_threads.size());
+    for (int i = 0; i < n; ++i) {
+        pfbs_plan *p = b->plans[i];
+        if (w[i].any) {
+            BatchFrontEntry &F = T.front[nf++];
+            memset(&F, 0, sizeof F);
+            F.pfb = p->pfb ? 1 : 0;
+            F.wg0 = wf;
+            if (!p->fourstep) {
+                F.kind = 0;
+                F.L = (int)p->N;
+                F.wgn = w[i].single_chunks;
+                F.a = w[i].single;
+            } else {
+                const Group &g = w[i].groups[0];
+                F.kind = 1;
+                F.L = (int)p->N2;
+                F.wgn = g.na * p->ntilesA;
+                F.a = g.fa;
+                const int ti = (int)(std::find(b->back_threads.begin(), b->back_threads.end(), row_threads(p)) -
+                                     b->back_threads.begin());
+                BatchBackEntry B;
+                memset(&B, 0, sizeof B);
+                B.L = (int)p->N1;
+                B.wg0 = wb[ti];
+                B.wgn = g.nc * p->ntilesB;
+                B.a = g.ba;
+                wb[ti] += B.wgn;
+                backs[ti].push_back(B);
+                lds_back[ti] = std::max(lds_back[ti], back_lds_bytes(p->gB, p->npol));
+            }
+            wf += F.wgn;
+            lds_front = std::max(lds_front, front_lds_bytes(p->gA, p->npol));
+            BatchTailEntry &R = T.tail[ntl++];
+            memset(&R, 0, sizeof R);
+            R.kind = 0;
+            R.r = w[i].ra;
+            R.gx = p->fourstep ? (int)((p->N2 / 8) * (p->N1 / 32)) : (int)((p->N + 255) / 256);
+            R.gy = w[i].n_dumps;
+            R.wg0 = wt;
+            R.wgn = R.gx * R.gy * p->nprod;
+            wt += R.wgn;
+        }
+        if (w[i].hist) {
+            BatchTailEntry &H = T.tail[ntl++];
+            memset(&H, 0, sizeof H);
+            H.kind = 1;
+            H.hdst = p->hist[p->hcur ^ 1];
+            H.fr = w[i].fr;
+            H.F = w[i].F;
+            H.H = p->P - 1;
+            H.frame_vec = p->frame_bytes / 16;
+            H.wg0 = wt;
+            H.wgn = (int)std::min<int64_t>(1024, (H.H * H.frame_vec + 255) / 256);
+            wt += H.wgn;
+        }
+    }
+    int off = 0;
+    std::vector<int> back_off(b->back_threads.size());
+    for (size_t t = 0; t < backs.size(); ++t) {
+        back_off[t] = off;
+        for (const BatchBackEntry &B : backs[t]) T.back[off++] = B;
+        nb[t] = (int)backs[t].size();
+    }
+    // ---- launch list (fixed topology: front, each row-pass size, tail)
+    // device addresses of the three tables (no host access to device memory)
+    char *dbase = reinterpret_cast<char *>(b->d_tab);
+    const BatchFrontEntry *d_front =
+        reinterpret_cast<const BatchFrontEntry *>(dbase + offsetof(pfbs_batch::Tables, front));
+    const BatchBackEntry *d_back =
+        reinterpret_cast<const BatchBackEntry *>(dbase + offsetof(pfbs_batch::Tables, back));
+    const BatchTailEntry *d_tail =
+        reinterpret_cast<const BatchTailEntry *>(dbase + offsetof(pfbs_batch::Tables, tail));
+    std::vector<BLaunch> L;
+    L.push_back({batch_front_fn(b->npol), wf, kTilePoints / 16 * b->npol, lds_front, d_front, nf});
+    for (size_t t = 0; t < b->back_threads.size(); ++t)
+        L.push_back({batch_back_fn(b->npol, b->back_threads[t]), wb[t], b->back_threads[t], lds_back[t],
+                     d_back + back_off[t], nb[t]});
+    L.push_back({batch_tail_fn(), wt, 256, 0, d_tail, ntl});
+
+    hipStream_t cs = (hipStream_t)stream;
+    hipStream_t s = use_graph ? b->gstream : cs;
+    pfbs_plan *p0 = b->plans[0];
+    PFBS_HIP(p0, hipSetDevice(p0->device));
+    if (use_graph) {
+        PFBS_HIP(p0, hipEventRecord(b->ev_in, cs));
+        PFBS_HIP(p0, hipStreamWaitEvent(s, b->ev_in, 0));
+    }
+    PFBS_HIP(p0, hipMemcpyAsync(b->d_tab, &T, sizeof T, hipMemcpyHostToDevice, s));
+    PFBS_HIP(p0, hipEventRecord(b->staged[k], s));
+    b->stage ^= 1;
+    if (!use_graph) {
+        for (const BLaunch &x : L) {
+            void *args[] = {(void *)&x.table, (void *)&x.n};
+            PFBS_HIP(p0, hipLaunchKernel(x.fn, dim3(x.grid > 0 ? x.grid : 1), dim3(x.threads), args, x.lds, s));
+        }
+    } else {
+        if (!b->gexec) {
+            PFBS_HIP(p0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipSuccess;
+            for (const BLaunch &x : L) {
+                void *args[] = {(void *)&x.table, (void *)&x.n};
+                if (le == hipSuccess)
+                    le = hipLaunchKernel(x.fn, dim3(x.grid > 0 ? x.grid : 1), dim3(x.threads), args, x.lds, s);
+            }
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess) return hip_fail(p0, le, "batch capture launch");
+            if (ce != hipSuccess) return hip_fail(p0, ce, "batch capture");
+            b->graph = g;
+            PFBS_HIP(p0, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+            // the kernel nodes, ordered as the launch list (a linear chain)
+            size_t nn = 0;
+            PFBS_HIP(p0, hipGraphGetNodes(b->graph, nullptr, &nn));
+            std::vector<hipGraphNode_t> nodes(nn);
+            PFBS_HIP(p0, hipGraphGetNodes(b->graph, nodes.data(), &nn));
+            b->gnodes.assign(L.size(), nullptr);
+            std::vector<bool> used(nn, false);
+            for (size_t li = 0; li < L.size(); ++li) {
+                for (size_t q = 0; q < nn; ++q) {
+                    if (used[q]) continue;
+                    hipKernelNodeParams kp;
+                    if (hipGraphKernelNodeGetParams(nodes[q], &kp) != hipSuccess) continue;
+                    if (kp.func == L[li].fn && (int)kp.blockDim.x == L[li].threads) {
+                        b->gnodes[li] = nodes[q];
+                        used[q] = true;
+                        break;
+                    }
+                }
+                if (!b->gnodes[li]) return fail(PFBS_ERR_DEVICE, "batch graph: kernel node %zu not found", li);
+            }
+        } else {
+            for (size_t li = 0; li < L.size(); ++li) {
+                const BLaunch &x = L[li];
+                void *args[] = {(void *)&x.table, (void *)&x.n};
+                hipKernelNodeParams kp;
+                memset(&kp, 0, sizeof kp);
+                kp.func = const_cast<void *>(x.fn);
+                kp.gridDim = dim3(x.grid > 0 ? x.grid : 1);
+                kp.blockDim = dim3(x.threads);
+                kp.sharedMemBytes = (unsigned)x.lds;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                PFBS_HIP(p0, hipGraphExecKernelNodeSetParams(b->gexec, b->gnodes[li], &kp));
+            }
+        }
+        PFBS_HIP(p0, hipGraphLaunch(b->gexec, s));
+        PFBS_HIP(p0, hipEventRecord(b->ev_out, s));
+        PFBS_HIP(p0, hipStreamWaitEvent(cs, b->ev_out, 0));
     }
     for (int i = 0; i < n; ++i) {
-        pfbs_status st = pfbs_execute(b->plans[i], d_blocks[i], n_samples[i], d_dumps[i], caps[i],
-                                      &n_dumps[i], stream);
-        if (st != PFBS_OK) return st;
+        commit(b->plans[i], w[i]);
+        n_dumps[i] = w[i].nd_out;
     }
     return PFBS_OK;
 }
@@ -732,7 +1051,11 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
 pfbs_status pfbs_batch_destroy(pfbs_batch *b) {
     if (!b) return PFBS_OK;
     if (b->magic != kMagic) return fail(PFBS_ERR_STATE, "not a live batch");
-    for (pfbs_plan *p : b->plans) pfbs_plan_destroy(p);
+    if (!b->plans.empty()) {
+        (void)hipSetDevice(b->plans[0]->device);
+        (void)hipDeviceSynchronize();
+    }
+    batch_free(b);
     b->magic = kDead;
     delete b;
     return PFBS_OK;

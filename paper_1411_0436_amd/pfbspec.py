@@ -25,6 +25,7 @@ EXPORTS = (
     "pfbs_execute", "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
     "pfbs_plan_get_info", "pfbs_last_error", "pfbs_batch_create", "pfbs_batch_execute",
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
+    "pfbs_autotune",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -43,6 +44,7 @@ class PlanDesc(ctypes.Structure):
         ("precision", ctypes.c_int32), ("device", ctypes.c_int32),
         ("custom_taps", ctypes.c_void_p), ("tune", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("split_n2", ctypes.c_int64), ("group_bytes", ctypes.c_int64),
+        ("col_run", ctypes.c_int32), ("stream_z", ctypes.c_int32),
     ]
 
 
@@ -87,12 +89,14 @@ def load(path: str = LIB_PATH):
     L.pfbs_batch_destroy.argtypes = [vp]
     L.pfbs_plan_timing.argtypes = [vp, i32]
     L.pfbs_plan_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), pi64, i32]
+    L.pfbs_autotune.argtypes = [ctypes.POINTER(PlanDesc), i64, i32, ctypes.POINTER(PlanDesc),
+                                ctypes.POINTER(ctypes.c_double)]
     L.pfbs_batch_plan.argtypes = [vp, i32]
     L.pfbs_batch_plan.restype = vp
     for name in ("pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_execute",
                  "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
                  "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy",
-                 "pfbs_plan_timing", "pfbs_plan_timing_read"):
+                 "pfbs_plan_timing", "pfbs_plan_timing_read", "pfbs_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -116,13 +120,15 @@ def _stream_ptr(stream) -> Optional[int]:
 
 def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_PFB, n_pol: int = 2,
               n_int: int = 1, precision: int = PREC_FP32, device: int = -1, custom_taps=None,
-              tune: int = 0, chunk: int = 0, split_n2: int = 0, group_bytes: int = 0):
+              tune: int = 0, chunk: int = 0, split_n2: int = 0, group_bytes: int = 0,
+              col_run: int = 0, stream_z: int = 0):
     """A PlanDesc; ``custom_taps`` (float64 numpy array) is kept alive on the
     returned object until the plan is created."""
     import numpy as np
     d = PlanDesc(N=N, P=P, window=window, mode=mode, n_pol=n_pol, n_int=n_int,
                  precision=precision, device=device, custom_taps=None, tune=tune,
-                 chunk=chunk, split_n2=split_n2, group_bytes=group_bytes)
+                 chunk=chunk, split_n2=split_n2, group_bytes=group_bytes,
+                 col_run=col_run, stream_z=stream_z)
     keep = None
     if custom_taps is not None:
         keep = np.ascontiguousarray(custom_taps, dtype=np.float64)
@@ -131,6 +137,19 @@ def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_P
         d.custom_taps = keep.ctypes.data
     d._keep = keep
     return d
+
+
+def autotune(block_samples: int = 0, max_candidates: int = 0, **desc_kw):
+    """Time candidate settings for a plan shape (see pfbs_autotune).
+    Returns (dict of the tuned fields, complex samples per second)."""
+    L = load()
+    d = make_desc(**desc_kw)
+    best = PlanDesc()
+    sps = ctypes.c_double(0.0)
+    _check(L.pfbs_autotune(ctypes.byref(d), block_samples, max_candidates, ctypes.byref(best),
+                           ctypes.byref(sps)))
+    fields = ("split_n2", "chunk", "col_run", "stream_z")
+    return {f: getattr(best, f) for f in fields}, sps.value
 
 
 class Plan:

@@ -1,0 +1,50 @@
+"""The autotuner: it times candidate settings on the device, returns a valid
+one, records it in the cache file, and plans built from the cache compute the
+same dumps as the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_0436_amd import pfbspec as pf
+from paper_1411_0436_amd import synth
+from tests.gpu_util import require_gpu, run_stream, within_fp32_bound
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_returns_valid_setting_and_caches_it(tmp_path, monkeypatch):
+    require_gpu()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PFBS_TUNE_CACHE", str(cache))
+    N = 8192
+    fields, sps = pf.autotune(block_samples=64 * N, max_candidates=8, N=N, P=8, n_pol=2, n_int=16)
+    assert sps > 0
+    assert fields["split_n2"] in (64, 128, 256, 512)
+    assert fields["chunk"] in (8, 16, 32, 64)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("pfbs-tune-v1 gfx950 8192 8 0 2 16 0 ")
+    plan = pf.Plan(N, 8, n_pol=2, n_int=16, tune=1)
+    info = plan.info()
+    assert info["split_n2"] == fields["split_n2"] and info["chunk"] == fields["chunk"]
+    x = synth.generate(synth.noise_only(2, 20.0, 77), 0, 60 * N)
+    dumps, _, _ = run_stream(plan, x, [23, 37])
+    ref = oracle.dumps(x, N, 8, oracle.taps(N, 8), False, 16)
+    assert dumps.shape[0] == ref.shape[0] == 3
+    for d in range(3):
+        assert within_fp32_bound(dumps[d], ref[d], N) <= 1.0
+
+
+def test_tune_without_cache_entry_keeps_defaults(tmp_path, monkeypatch):
+    require_gpu()
+    monkeypatch.setenv("PFBS_TUNE_CACHE", str(tmp_path / "empty.txt"))
+    plan = pf.Plan(32768, 8, n_pol=2, n_int=4, tune=1)
+    assert plan.info()["split_n2"] == 256
+
+
+def test_single_pass_shape_tunes_chunk_only(tmp_path, monkeypatch):
+    require_gpu()
+    monkeypatch.delenv("PFBS_TUNE_CACHE", raising=False)
+    fields, sps = pf.autotune(block_samples=256 * 1024, N=1024, P=8, n_pol=1, n_int=64)
+    assert sps > 0 and fields["split_n2"] == 0 and fields["col_run"] == 0
