@@ -9,6 +9,40 @@ namespace pfbs {
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 
+// A pointer read from device memory is a generic (flat) address to the
+// compiler, and accesses through it become flat loads and stores, which take
+// the LDS/scratch aperture checks.  Every buffer of this library is global
+// device memory; passing the address through an integer into the global
+// address space lets the compiler emit global loads and stores instead.
+template <class T>
+__device__ __forceinline__ T *as_global(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(unsigned long long)p;
+}
+
+__device__ __forceinline__ void globalise(Frames &f) {
+    f.blk = as_global(f.blk);
+    f.hist = as_global(f.hist);
+}
+__device__ __forceinline__ void globalise(FrontArgs &a) {
+    globalise(a.fr);
+    a.taps = as_global(a.taps);
+    a.g.tw = as_global(a.g.tw);
+    a.Z = as_global(a.Z);
+    a.tw4 = as_global(a.tw4);
+    a.part = as_global(a.part);
+}
+__device__ __forceinline__ void globalise(BackArgs &a) {
+    a.Z = as_global(a.Z);
+    a.g.tw = as_global(a.g.tw);
+    a.part = as_global(a.part);
+}
+__device__ __forceinline__ void globalise(ReduceArgs &a) {
+    a.part = as_global(a.part);
+    a.carried_in = as_global(a.carried_in);
+    a.carried_out = as_global(a.carried_out);
+    a.out = as_global(a.out);
+}
+
 // --------------------------------------------------------------- complex --
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

@@ -102,13 +102,16 @@ __global__ __launch_bounds__(256) void k_history(uint4 *dst, Frames fr, long lon
 }
 
 // Batched tail: dump reductions and tap-history copies of every sub-band.
-__global__ __launch_bounds__(256) void k_batch_tail(const BatchTailEntry *t, int n) {
+__global__ __launch_bounds__(256) void k_batch_tail(const BatchTailEntry *__restrict__ t, int n) {
     if (n <= 0) return;
     int e = 0;
     while (e + 1 < n && (int)blockIdx.x >= t[e + 1].wg0) ++e;
-    const BatchTailEntry &E = t[e];
-    const int vb = blockIdx.x - E.wg0;
-    if (vb < 0 || vb >= E.wgn) return;
+    const int vb = blockIdx.x - t[e].wg0;
+    if (vb < 0 || vb >= t[e].wgn) return;
+    BatchTailEntry E = t[e];  // private copy, as in the batched FFT kernels
+    globalise(E.r);
+    globalise(E.fr);
+    E.hdst = as_global(E.hdst);
     if (E.kind == 0) {
         const int per_z = E.gx * E.gy;
         const int bz = vb / per_z, rem = vb - bz * per_z;
@@ -293,11 +296,6 @@ hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long 
         if (pfb) hipLaunchKernelGGL((k_debug_pfb<1, true>), grid, block, 0, s, y, fr, taps, N, P, j_lo, j_hi);
         else hipLaunchKernelGGL((k_debug_pfb<1, false>), grid, block, 0, s, y, fr, taps, N, P, j_lo, j_hi);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_tail(const BatchTailEntry *t, int n, int total_wg, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_tail, dim3(total_wg > 0 ? total_wg : 1), dim3(256), 0, s, t, n);
     return hipGetLastError();
 }
 

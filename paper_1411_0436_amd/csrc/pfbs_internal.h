@@ -112,16 +112,10 @@ struct BatchTailEntry {
     int H;
 };
 
-hipError_t launch_batch_front(const BatchFrontEntry *t, int n, int total_wg, int npol, size_t lds,
-                              hipStream_t s);
-hipError_t launch_batch_back(const BatchBackEntry *t, int n, int total_wg, int npol, int threads,
-                             size_t lds, hipStream_t s);
-hipError_t launch_batch_tail(const BatchTailEntry *t, int n, int total_wg, hipStream_t s);
-// Kernel symbol and block size of a batched launch, for HIP graph node updates.
-const void *batch_front_fn(int npol);
-const void *batch_back_fn(int npol, int threads);
+// Kernels of the batched launches (see k_batch.hip): one per variant.
+const void *multi_front_fn(int npol, int kind, int pfb, int L);
+const void *multi_back_fn(int npol, int L);
 const void *batch_tail_fn();
-size_t back_lds_bytes_for(int L, int npol);
 
 }  // namespace pfbs
 

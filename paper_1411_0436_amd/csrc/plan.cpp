@@ -121,8 +121,12 @@ struct pfbs_batch {
     uint32_t magic;
     std::vector<pfbs_plan *> plans;
     int npol;
-    std::vector<int> back_threads;   // row-pass workgroup sizes present (fixed launch list)
-    // entry tables: device copy read by the dispatchers, two pinned staging copies
+    // kernel variants present (fixed by the sub-band shapes): one launch each
+    struct FVar { int kind, pfb, L; std::vector<int> plans; };
+    struct BVar { int fvar, L; std::vector<int> plans; };   // row passes of one column-pass group
+    std::vector<FVar> fvars;
+    std::vector<BVar> bvars;
+    // entry tables: device copy read by the kernels, two pinned staging copies
     struct Tables {
         BatchFrontEntry front[kMaxBatch];
         BatchBackEntry back[kMaxBatch];
@@ -132,12 +136,13 @@ struct pfbs_batch {
     Tables *h_tab[2];
     hipEvent_t staged[2];
     int stage;
-    // HIP graph of the launch sequence, captured on first use
+    // HIP graph of the launch sequence with upper-bound grids, captured on
+    // first use for one set of block sizes
     hipStream_t gstream;
     hipEvent_t ev_in, ev_out;
     hipGraph_t graph;
     hipGraphExec_t gexec;
-    std::vector<hipGraphNode_t> gnodes;   // in launch-list order
+    std::vector<int64_t> gsizes;
 };
 
 namespace {
@@ -799,10 +804,7 @@ void batch_free(pfbs_batch *b) {
     if (b->d_tab) (void)hipFree(b->d_tab);
 }
 
-int row_threads(const pfbs_plan *p) { return back_tile(p->N1) / 16 * p->npol; }
-
-// One kernel launch of a batched block: which dispatcher, its grid, LDS and
-// entry table.
+// One kernel launch of a batched block.
 struct BLaunch {
     const void *fn;
     int grid, threads;
@@ -810,6 +812,17 @@ struct BLaunch {
     const void *table;
     int n;
 };
+
+// Upper bounds on the workgroups of one sub-band's launches for a block of F
+// frames (graph replays keep these grids; surplus workgroups exit at once).
+int64_t max_chunks(const pfbs_plan *p, int64_t F) { return F / p->G + F / p->n_int + 3; }
+int64_t max_dumps(const pfbs_plan *p, int64_t F) { return F / p->n_int + 2; }
+int reduce_gx(const pfbs_plan *p) {
+    return p->fourstep ? (int)((p->N2 / 8) * (p->N1 / 32)) : (int)((p->N + 255) / 256);
+}
+int hist_wg(const pfbs_plan *p) {
+    return (int)std::min<int64_t>(1024, ((int64_t)(p->P - 1) * (p->frame_bytes / 16) + 255) / 256);
+}
 
 }  // namespace
 
@@ -840,15 +853,25 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
             break;
         }
         b->plans.push_back(p);
+        const int kind = p->fourstep ? 1 : 0, pfb = p->pfb ? 1 : 0, L = (int)p->gA.L;
+        auto fv = std::find_if(b->fvars.begin(), b->fvars.end(), [&](const pfbs_batch::FVar &v) {
+            return v.kind == kind && v.pfb == pfb && v.L == L;
+        });
+        if (fv == b->fvars.end()) b->fvars.push_back({kind, pfb, L, {i}});
+        else fv->plans.push_back(i);
         if (p->fourstep) {
-            const int t = row_threads(p);
-            if (std::find(b->back_threads.begin(), b->back_threads.end(), t) == b->back_threads.end())
-                b->back_threads.push_back(t);
+            const int fi = (int)(std::find_if(b->fvars.begin(), b->fvars.end(), [&](const pfbs_batch::FVar &v) {
+                                     return v.kind == kind && v.pfb == pfb && v.L == L;
+                                 }) - b->fvars.begin());
+            auto bv = std::find_if(b->bvars.begin(), b->bvars.end(), [&](const pfbs_batch::BVar &v) {
+                return v.fvar == fi && v.L == (int)p->N1;
+            });
+            if (bv == b->bvars.end()) b->bvars.push_back({fi, (int)p->N1, {i}});
+            else bv->plans.push_back(i);
         }
     }
     hipError_t e = hipSuccess;
     if (st == PFBS_OK) {
-        std::sort(b->back_threads.begin(), b->back_threads.end());
         if ((e = hipMalloc((void **)&b->d_tab, sizeof(pfbs_batch::Tables))) == hipSuccess &&
             (e = hipHostMalloc((void **)&b->h_tab[0], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
             (e = hipHostMalloc((void **)&b->h_tab[1], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
@@ -881,59 +904,110 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
         pfbs_status st = prepare(b->plans[i], d_blocks[i], n_samples[i], d_dumps[i], caps[i], true, w[i]);
         if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
     }
+    pfbs_plan *p0 = b->plans[0];
+    // a graph replays fixed grids: recapture when the block sizes change
+    const std::vector<int64_t> sizes(n_samples, n_samples + n);
+    if (use_graph && b->gexec && sizes != b->gsizes) {
+        (void)hipGraphExecDestroy(b->gexec);
+        (void)hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+    }
     // ---- entry tables (host staging buffer k; wait until its last upload is done)
     const int k = b->stage;
     hipError_t e = hipEventSynchronize(b->staged[k]);
     if (e != hipSuccess) return hip_fail(nullptr, e, "batch staging");
     pfbs_batch::Tables &T = *b->h_tab[k];
-    int nf = 0, ntl = 0, wf = 0, wt = 0;
-    size_t lds_front = 0;
-    std::vector<int> nb(b->back_threads.size(), 0), wb(b->back_threads.size(), 0);
-    std::vector<size_t> lds_back(b->back_threads.size(), 0);
-    // back entries of each workgroup size are stored contiguously per size
-    std::vector<std::vector<BatchBackEntry>> backs(b->back_threads.size());
-    for (int i = 0; i < n; ++i) {
-        pfbs_plan *p = b->plans[i];
-        if (w[i].any) {
-            BatchFrontEntry &F = T.front[nf++];
-            memset(&F, 0, sizeof F);
-            F.pfb = p->pfb ? 1 : 0;
-            F.wg0 = wf;
-            if (!p->fourstep) {
-                F.kind = 0;
-                F.L = (int)p->N;
-                F.wgn = w[i].single_chunks;
-                F.a = w[i].single;
-            } else {
-                const Group &g = w[i].groups[0];
-                F.kind = 1;
-                F.L = (int)p->N2;
-                F.wgn = g.na * p->ntilesA;
-                F.a = g.fa;
-                const int ti = (int)(std::find(b->back_threads.begin(), b->back_threads.end(), row_threads(p)) -
-                                     b->back_threads.begin());
-                BatchBackEntry B;
-                memset(&B, 0, sizeof B);
-                B.L = (int)p->N1;
-                B.wg0 = wb[ti];
-                B.wgn = g.nc * p->ntilesB;
-                B.a = g.ba;
-                wb[ti] += B.wgn;
-                backs[ti].push_back(B);
-                lds_back[ti] = std::max(lds_back[ti], back_lds_bytes(p->gB, p->npol));
+    char *dbase = reinterpret_cast<char *>(b->d_tab);
+    const BatchFrontEntry *d_front =
+        reinterpret_cast<const BatchFrontEntry *>(dbase + offsetof(pfbs_batch::Tables, front));
+    const BatchBackEntry *d_back =
+        reinterpret_cast<const BatchBackEntry *>(dbase + offsetof(pfbs_batch::Tables, back));
+    const BatchTailEntry *d_tail =
+        reinterpret_cast<const BatchTailEntry *>(dbase + offsetof(pfbs_batch::Tables, tail));
+    std::vector<BLaunch> L, LF, LB;
+    int nf = 0;
+    for (const pfbs_batch::FVar &v : b->fvars) {  // one launch per column/single-pass variant
+        const int first = nf;
+        int wg = 0, wg_max = 0;
+        size_t lds = 0;
+        for (int i : v.plans) {
+            pfbs_plan *p = b->plans[i];
+            const int64_t F = n_samples[i] / p->N;
+            BatchFrontEntry &E = T.front[nf++];
+            memset(&E, 0, sizeof E);
+            E.kind = v.kind;
+            E.pfb = v.pfb;
+            E.L = v.L;
+            E.wg0 = wg;
+            if (w[i].any) {
+                if (v.kind == 0) {
+                    E.a = w[i].single;
+                    E.wgn = w[i].single_chunks;
+                } else {
+                    E.a = w[i].groups[0].fa;
+                    E.wgn = w[i].groups[0].na * p->ntilesA;
+                }
             }
-            wf += F.wgn;
-            lds_front = std::max(lds_front, front_lds_bytes(p->gA, p->npol));
-            BatchTailEntry &R = T.tail[ntl++];
-            memset(&R, 0, sizeof R);
-            R.kind = 0;
-            R.r = w[i].ra;
-            R.gx = p->fourstep ? (int)((p->N2 / 8) * (p->N1 / 32)) : (int)((p->N + 255) / 256);
-            R.gy = w[i].n_dumps;
-            R.wg0 = wt;
-            R.wgn = R.gx * R.gy * p->nprod;
-            wt += R.wgn;
+            // entries start on a multiple of 8 workgroups: workgroups are dealt
+            // to the 8 XCDs round-robin and the column pass maps its tiles to
+            // XCDs by block id
+            wg += (E.wgn + 7) & ~7;
+            wg_max += (int)((v.kind == 0 ? max_chunks(p, F)
+                                         : p->ntilesA * ((F + std::max(1, p->ga_force) - 1) / std::max(1, p->ga_force))) + 7) & ~7;
+            lds = std::max(lds, front_lds_bytes(p->gA, p->npol));
         }
+        LF.push_back({multi_front_fn(b->npol, v.kind, v.pfb, v.L), use_graph ? wg_max : wg,
+                      kTilePoints / 16 * b->npol, lds, d_front + first, nf - first});
+    }
+    int nbk = 0;
+    for (const pfbs_batch::BVar &v : b->bvars) {  // one launch per row-pass variant
+        const int first = nbk;
+        int wg = 0, wg_max = 0;
+        size_t lds = 0;
+        int threads = 0;
+        for (int i : v.plans) {
+            pfbs_plan *p = b->plans[i];
+            const int64_t F = n_samples[i] / p->N;
+            BatchBackEntry &E = T.back[nbk++];
+            memset(&E, 0, sizeof E);
+            E.L = v.L;
+            E.wg0 = wg;
+            if (w[i].any) {
+                E.a = w[i].groups[0].ba;
+                E.wgn = w[i].groups[0].nc * p->ntilesB;
+            }
+            wg += E.wgn;
+            wg_max += (int)(p->ntilesB * max_chunks(p, F));
+            lds = std::max(lds, back_lds_bytes(p->gB, p->npol));
+            threads = back_tile(p->N1) / 16 * p->npol;
+        }
+        LB.push_back({multi_back_fn(b->npol, v.L), use_graph ? wg_max : wg, threads, lds, d_back + first,
+                      nbk - first});
+    }
+    // each column-pass group is followed by its own row passes, so that their
+    // intermediate is read back while it is still in the Infinity Cache
+    for (size_t fi = 0; fi < LF.size(); ++fi) {
+        L.push_back(LF[fi]);
+        for (size_t bi = 0; bi < b->bvars.size(); ++bi)
+            if (b->bvars[bi].fvar == (int)fi) L.push_back(LB[bi]);
+    }
+    int ntl = 0, wt = 0, wt_max = 0;
+    for (int i = 0; i < n; ++i) {  // dump reductions and history copies: one launch
+        pfbs_plan *p = b->plans[i];
+        const int64_t F = n_samples[i] / p->N;
+        BatchTailEntry &R = T.tail[ntl++];
+        memset(&R, 0, sizeof R);
+        R.kind = 0;
+        R.gx = reduce_gx(p);
+        R.wg0 = wt;
+        if (w[i].any) {
+            R.r = w[i].ra;
+            R.gy = w[i].n_dumps;
+            R.wgn = R.gx * R.gy * p->nprod;
+        }
+        wt += R.wgn;
+        wt_max += (int)(R.gx * max_dumps(p, F) * p->nprod);
         if (w[i].hist) {
             BatchTailEntry &H = T.tail[ntl++];
             memset(&H, 0, sizeof H);
@@ -944,36 +1018,15 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             H.H = p->P - 1;
             H.frame_vec = p->frame_bytes / 16;
             H.wg0 = wt;
-            H.wgn = (int)std::min<int64_t>(1024, (H.H * H.frame_vec + 255) / 256);
+            H.wgn = hist_wg(p);
             wt += H.wgn;
+            wt_max += H.wgn;
         }
     }
-    int off = 0;
-    std::vector<int> back_off(b->back_threads.size());
-    for (size_t t = 0; t < backs.size(); ++t) {
-        back_off[t] = off;
-        for (const BatchBackEntry &B : backs[t]) T.back[off++] = B;
-        nb[t] = (int)backs[t].size();
-    }
-    // ---- launch list (fixed topology: front, each row-pass size, tail)
-    // device addresses of the three tables (no host access to device memory)
-    char *dbase = reinterpret_cast<char *>(b->d_tab);
-    const BatchFrontEntry *d_front =
-        reinterpret_cast<const BatchFrontEntry *>(dbase + offsetof(pfbs_batch::Tables, front));
-    const BatchBackEntry *d_back =
-        reinterpret_cast<const BatchBackEntry *>(dbase + offsetof(pfbs_batch::Tables, back));
-    const BatchTailEntry *d_tail =
-        reinterpret_cast<const BatchTailEntry *>(dbase + offsetof(pfbs_batch::Tables, tail));
-    std::vector<BLaunch> L;
-    L.push_back({batch_front_fn(b->npol), wf, kTilePoints / 16 * b->npol, lds_front, d_front, nf});
-    for (size_t t = 0; t < b->back_threads.size(); ++t)
-        L.push_back({batch_back_fn(b->npol, b->back_threads[t]), wb[t], b->back_threads[t], lds_back[t],
-                     d_back + back_off[t], nb[t]});
-    L.push_back({batch_tail_fn(), wt, 256, 0, d_tail, ntl});
+    L.push_back({batch_tail_fn(), use_graph ? wt_max : wt, 256, 0, d_tail, ntl});
 
     hipStream_t cs = (hipStream_t)stream;
     hipStream_t s = use_graph ? b->gstream : cs;
-    pfbs_plan *p0 = b->plans[0];
     PFBS_HIP(p0, hipSetDevice(p0->device));
     if (use_graph) {
         PFBS_HIP(p0, hipEventRecord(b->ev_in, cs));
@@ -984,6 +1037,7 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
     b->stage ^= 1;
     if (!use_graph) {
         for (const BLaunch &x : L) {
+            if (x.n == 0) continue;
             void *args[] = {(void *)&x.table, (void *)&x.n};
             PFBS_HIP(p0, hipLaunchKernel(x.fn, dim3(x.grid > 0 ? x.grid : 1), dim3(x.threads), args, x.lds, s));
         }
@@ -1002,40 +1056,7 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             if (ce != hipSuccess) return hip_fail(p0, ce, "batch capture");
             b->graph = g;
             PFBS_HIP(p0, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
-            // the kernel nodes, ordered as the launch list (a linear chain)
-            size_t nn = 0;
-            PFBS_HIP(p0, hipGraphGetNodes(b->graph, nullptr, &nn));
-            std::vector<hipGraphNode_t> nodes(nn);
-            PFBS_HIP(p0, hipGraphGetNodes(b->graph, nodes.data(), &nn));
-            b->gnodes.assign(L.size(), nullptr);
-            std::vector<bool> used(nn, false);
-            for (size_t li = 0; li < L.size(); ++li) {
-                for (size_t q = 0; q < nn; ++q) {
-                    if (used[q]) continue;
-                    hipKernelNodeParams kp;
-                    if (hipGraphKernelNodeGetParams(nodes[q], &kp) != hipSuccess) continue;
-                    if (kp.func == L[li].fn && (int)kp.blockDim.x == L[li].threads) {
-                        b->gnodes[li] = nodes[q];
-                        used[q] = true;
-                        break;
-                    }
-                }
-                if (!b->gnodes[li]) return fail(PFBS_ERR_DEVICE, "batch graph: kernel node %zu not found", li);
-            }
-        } else {
-            for (size_t li = 0; li < L.size(); ++li) {
-                const BLaunch &x = L[li];
-                void *args[] = {(void *)&x.table, (void *)&x.n};
-                hipKernelNodeParams kp;
-                memset(&kp, 0, sizeof kp);
-                kp.func = const_cast<void *>(x.fn);
-                kp.gridDim = dim3(x.grid > 0 ? x.grid : 1);
-                kp.blockDim = dim3(x.threads);
-                kp.sharedMemBytes = (unsigned)x.lds;
-                kp.kernelParams = args;
-                kp.extra = nullptr;
-                PFBS_HIP(p0, hipGraphExecKernelNodeSetParams(b->gexec, b->gnodes[li], &kp));
-            }
+            b->gsizes = sizes;
         }
         PFBS_HIP(p0, hipGraphLaunch(b->gexec, s));
         PFBS_HIP(p0, hipEventRecord(b->ev_out, s));
