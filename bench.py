@@ -40,7 +40,46 @@ WORKLOADS = {
     "c2-direct": dict(N=32768, P=1, direct=True, n_pol=2, n_int=1024, block=1 << 24, blocks=8, spec="c2"),
     "c3": dict(N=1 << 19, P=8, direct=False, n_pol=2, n_int=64, block=1 << 26, blocks=2, spec="c3"),
     "c1": dict(N=1024, P=8, direct=False, n_pol=1, n_int=1017, block=1 << 20, blocks=1, spec="c1"),
+    # precision study: the c2 stream at three lengths (run with --precision)
+    "c4-4096": dict(N=4096, P=8, direct=False, n_pol=2, n_int=1024, block=1 << 24, blocks=8, spec="c2"),
+    "c4-65536": dict(N=65536, P=8, direct=False, n_pol=2, n_int=1024, block=1 << 24, blocks=8, spec="c2"),
+    "c4-524288": dict(N=1 << 19, P=8, direct=False, n_pol=2, n_int=128, block=1 << 24, blocks=8, spec="c2"),
 }
+PRECISIONS = {"fp32": 0, "fp16": 1, "fp16x2": 2}
+
+# Sources that define the spectrometer kernels: a traffic summary under
+# profiles/ applies only while their digest is unchanged.
+KERNEL_SOURCES = ["fft_common.h", "fft_bodies.h", "k_single.hip", "k_fourstep.hip", "pfbs_internal.h"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1411_0436_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the counter summary in profiles/
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is
+    none for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.txt" % (kernel, workload, precision))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha1") != kernel_digest():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _gen_piece(args):
@@ -79,6 +118,21 @@ def flops_per_pol_sample(kind, w, N1, N2):
         return 4 * P + 5 * np.log2(N2) + 6
     if kind == "row_pass":
         return 5 * np.log2(N1) + prods
+    return 0.0
+
+
+def bytes_per_pol_sample(kind, w, G):
+    """Algorithmic HBM bytes per complex pol-sample of one kernel: the int8
+    input (2 B), the complex FP32 intermediate of the two-pass FFT (8 B
+    written by the column pass, 8 B read by the row pass) and the partial
+    sums (4 B per product and bin per chunk of G spectra)."""
+    part = 4.0 * (4 if w["n_pol"] == 2 else 1) / (G * w["n_pol"])
+    if kind == "single_pass":
+        return 2.0 + part
+    if kind == "column_pass":
+        return 2.0 + 8.0
+    if kind == "row_pass":
+        return 8.0 + part
     return 0.0
 
 
@@ -143,21 +197,32 @@ def bench_subbands(args):
     return results, t_gen
 
 
-def cpu_baseline(w, blocks, budget_spectra):
+def cpu_baseline(w, blocks, budget_spectra, min_seconds=10.0):
+    """The FP64 oracle, as written, on the host cores: the first
+    `budget_spectra` spectra of the stream (0 = every spectrum of it), run
+    again over the same sample until at least `min_seconds` have passed."""
     import oracle
     n_thr = len(os.sched_getaffinity(0))
     N, P, direct = w["N"], w["P"], w["direct"]
-    need = budget_spectra + (1 if direct else P) - 1
-    x = np.concatenate(blocks)[:need * N] if blocks[0].shape[0] < need * N else blocks[0][:need * N]
+    x = np.concatenate(blocks)
+    total = oracle.num_spectra(x.shape[0], N, P, direct)
+    S = total if budget_spectra <= 0 else min(budget_spectra, total)
+    x = x[:(S + (1 if direct else P) - 1) * N]
     h = None if direct else oracle.taps(N, P)
     oracle.integrate(x, N, P, h, direct, 0, 1, n_thr)  # warm (page in, build)
+    reps = 0
     t = time.perf_counter()
-    oracle.integrate(x, N, P, h, direct, 0, budget_spectra, n_thr)
-    dt = time.perf_counter() - t
-    samples = budget_spectra * N * w["n_pol"]
+    while True:
+        oracle.integrate(x, N, P, h, direct, 0, S, n_thr)
+        reps += 1
+        dt = time.perf_counter() - t
+        if dt >= min_seconds:
+            break
+    samples = reps * S * N * w["n_pol"]
     return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": n_thr, "kind": "oracle",
-            "sample": "first %d spectra (N=%d, %s, %d pol) of the same stream, FP64, %d threads, %.2f s"
-                      % (budget_spectra, N, "direct" if direct else "P=%d PFB" % P, w["n_pol"], n_thr, dt)}
+            "sample": "%d spectra (%s of the stream; N=%d, %s, %d pol), FP64, %d threads, %d pass(es) in %.1f s"
+                      % (S, "all" if S == total else "the first %d" % S, N,
+                         "direct" if direct else "P=%d PFB" % P, w["n_pol"], n_thr, reps, dt)}
 
 
 def main():
@@ -166,8 +231,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c5"])
-    ap.add_argument("--cpu-spectra", type=int, default=1024)
+    ap.add_argument("--cpu-spectra", type=int, default=0,
+                    help="spectra of the stream the CPU oracle is timed on (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
     ap.add_argument("--sub-block", type=int, default=SUB_BLOCK,
                     help="c5: time samples per sub-band per block (a multiple of 2^19)")
     ap.add_argument("--split-n2", type=int, default=0)
@@ -221,7 +288,7 @@ def main():
     dev_blocks = [torch.from_numpy(b).cuda() for b in host_blocks]
     plan = pf.Plan(N, w["P"], mode=pf.MODE_DIRECT if w["direct"] else pf.MODE_PFB, n_pol=n_pol,
                    n_int=w["n_int"], split_n2=args.split_n2, chunk=args.chunk,
-                   group_bytes=args.group_mb << 20)
+                   group_bytes=args.group_mb << 20, precision=PRECISIONS[args.precision])
     info = plan.info()
     cap = max(plan.dumps_in(w["block"]) + 1, 2)
     dumps = torch.empty((cap, plan.n_prod, N), dtype=torch.float32, device="cuda")
@@ -254,7 +321,10 @@ def main():
     avg_ms = dom_ms / max(dom_n, 1)
     pol_samples_per_launch = samples_per_step * args.steps / max(dom_n, 1)
     fl = flops_per_pol_sample(dom, w, info["split_n1"], info["split_n2"]) * pol_samples_per_launch
-    achieved = fl / (avg_ms * 1e-3) / 1e12
+    by = bytes_per_pol_sample(dom, w, info["chunk"]) * pol_samples_per_launch
+    tflops = fl / (avg_ms * 1e-3) / 1e12
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, args.workload, args.precision)
     bytes_in = 2.0 * value * 1e9
     out = {
         "metric": "Gsamples/s PFB+FFT+integrate (dual-pol) at N=32K..512K; MFMA vs FP32 at 1e-5",
@@ -267,15 +337,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "fp16x2": "f16x2 (f32 accumulate)"}[args.precision],
         "data": "synthetic (seeded int8 noise + tones, device-resident blocks)",
         "config": {"workload": args.workload, "N": N, "P": w["P"], "mode": "direct" if w["direct"] else "pfb",
                    "n_pol": n_pol, "n_int": w["n_int"], "block_samples": w["block"], "blocks": w["blocks"],
+                   "precision": args.precision,
                    "split_n1": info["split_n1"], "split_n2": info["split_n2"], "chunk": info["chunk"]},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": round(tflops, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                     "avg_launch_ms": round(avg_ms, 5)},
+                     "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "avg_launch_ms": round(avg_ms, 5),
+                     "flops_per_launch": round(fl),
+                     # the same launch seen from HBM: its input/intermediate bytes per second
+                     "hbm_bytes_per_launch": round(by), "hbm_GBps": round(achieved, 1),
+                     "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
         "hbm_input_frac": round(bytes_in / 1e9 / HBM_PEAK_GBS, 4),
         "bandwidth_per_pol_GHz": round(value / n_pol, 3),
         "kernel_ms": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt.items() if v[1]},

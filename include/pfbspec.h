@@ -72,9 +72,15 @@ typedef enum {
 typedef enum { PFBS_MODE_PFB = 0, PFBS_MODE_DIRECT = 1 } pfbs_mode;
 
 /* Arithmetic of the FFT.  FP32: every stage on the vector ALUs in float.
- * MFMA_FP16: radix-16 stages as 16x16 DFT-matrix products on the FP16 matrix
- * cores with FP32 accumulation, single FP16 operands.  MFMA_FP16X2: the same
- * with operands split into FP16 hi + lo pairs (three products per stage). */
+ * MFMA_FP16: each radix-16 stage as a product with the 16x16 DFT matrix on
+ * the FP16 matrix cores (v_mfma_f32_16x16x32_f16, FP32 accumulation), matrix
+ * and data rounded to single FP16 values after a per-butterfly power-of-two
+ * scaling; about 3 significant decimal digits.  MFMA_FP16X2: matrix and data
+ * split into FP16 hi + lo pairs, three products per stage (Wlo*hi + Whi*lo +
+ * Whi*hi); accuracy of the FP32 path.  The first radix-2/4/8 stage, the
+ * inter-stage and four-step twiddles, the pre-filter, the products and the
+ * accumulation stay FP32 in every precision.  Batches (pfbs_batch_create)
+ * take FP32 plans only. */
 typedef enum {
     PFBS_PREC_FP32 = 0,
     PFBS_PREC_MFMA_FP16 = 1,

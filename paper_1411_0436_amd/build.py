@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfbspec.so")
+RUNNER = os.path.join(HERE, "pfbs_run")
 SOURCES = ["k_single.hip", "k_fourstep.hip", "k_batch.hip", "k_aux.hip", "plan.cpp", "autotune.cpp"]
 HEADERS = ["pfbs_internal.h", "fft_common.h", os.path.join("..", "..", "include", "pfbspec.h")]
 
@@ -24,6 +25,8 @@ FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # matrix-core results in ordinary VGPRs (no accumulator-register copies)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(ROOT, "include"),
 ]
 
@@ -62,6 +65,14 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the plain C-ABI driver (for hardware-counter runs and as a C example)
+    tmp = RUNNER + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-o", tmp, os.path.join(CSRC, "pfbs_run.cpp"), "-L" + HERE, "-lpfbspec",
+                             "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, RUNNER)
     return LIB
 
 

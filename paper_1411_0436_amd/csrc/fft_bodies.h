@@ -14,7 +14,7 @@ namespace pfbs {
 // LDS FFT; a thread accumulates the products of fixed output bins of one
 // column in registers; at the end of the chunk the T columns are summed in
 // column order and written as the chunk's partial sum.
-template <int NPOL, bool PFB, int L>
+template <int NPOL, bool PFB, int L, int PREC = 0>
 __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
@@ -32,6 +32,8 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
     const int P = PFB ? a.P : 1;
     // column and butterfly owned in the last radix-16 pass
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+    MfmaW Wm{};
+    if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
 
     float acc[BINS][NP];
 #pragma unroll
@@ -75,16 +77,18 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
         }
         __syncthreads();
         float2 v[16];
-        fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
+        fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, NPOL == 1);
         if constexpr (NPOL == 2) {
             // X and Y of a bin meet through LDS (natural order)
+            if constexpr (!FftPrec<PREC>::IN_LDS) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
-                sre[ad] = v[r].x;
-                sim[ad] = v[r].y;
+                for (int r = 0; r < 16; ++r) {
+                    const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
+                    sre[ad] = v[r].x;
+                    sim[ad] = v[r].y;
+                }
+                __syncthreads();
             }
-            __syncthreads();
 #pragma unroll
             for (int i = 0; i < BINS; ++i) {
                 const int e = tid + NB * i;
@@ -96,6 +100,8 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
             }
             __syncthreads();
         } else {
+            // v was read back from LDS, which the next step overwrites
+            if constexpr (FftPrec<PREC>::IN_LDS) __syncthreads();
             if (j0 + c_own < je) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
@@ -137,7 +143,7 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
 //   rows of Z), the polarisation products and their accumulation in registers
 //   over the spectra of a chunk; the chunk's sums are written at
 //   u = k2*N1 + k1 (the reduction restores channel order).
-template <int NPOL, bool PFB, int L>
+template <int NPOL, bool PFB, int L, int PREC = 0>
 __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int nblk) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
@@ -172,6 +178,8 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
     // W_N^(n1 k2) of this thread's column, k2 = bb + r*L/16
     const float2 *tw4 = a.tw4 + (unsigned)((n1_0 + c_own) * L + bb_own);
+    MfmaW Wm{};
+    if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
 
     for (long long j = js; j < je; ++j) {
         float2 y[PTS][NPOL];
@@ -205,8 +213,9 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
         }
         __syncthreads();
         float2 v[16];
-        fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
-        // ---- twiddle W_N^(n1 k2), back to LDS in natural order
+        fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, true);
+        // ---- twiddle W_N^(n1 k2), back to LDS in natural order (each thread
+        // rewrites the positions it has just read)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int k2 = bb_own + r * G::L16;
@@ -243,7 +252,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 // short rows still give many small workgroups.
 template <int L> struct BackTile { static constexpr int TP = L < 1024 ? 1024 : L; };
 
-template <int NPOL, int L>
+template <int NPOL, int L, int PREC = 0>
 __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
     typedef Geom<L, BackTile<L>::TP> G;
     constexpr int NB = G::TPP * NPOL;
@@ -260,6 +269,8 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
     const long long N = a.N;
     const int k2_0 = tile * G::T;
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+    MfmaW Wm{};
+    if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
 
     float acc[BINS][NP];
 #pragma unroll
@@ -289,15 +300,17 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
         }
         __syncthreads();
         float2 v[16];
-        fft_plane<G>(sre, sim, pol, lt, a.g.tw, v);
+        fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, NPOL == 1);
         if constexpr (NPOL == 2) {
+            if constexpr (!FftPrec<PREC>::IN_LDS) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
-                sre[ad] = v[r].x;
-                sim[ad] = v[r].y;
+                for (int r = 0; r < 16; ++r) {
+                    const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
+                    sre[ad] = v[r].x;
+                    sim[ad] = v[r].y;
+                }
+                __syncthreads();
             }
-            __syncthreads();
 #pragma unroll
             for (int i = 0; i < BINS; ++i) {
                 const int e = tid + NB * i;
@@ -307,6 +320,7 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
             }
             __syncthreads();
         } else {
+            if constexpr (FftPrec<PREC>::IN_LDS) __syncthreads();
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
         }

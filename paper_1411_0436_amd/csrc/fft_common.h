@@ -237,6 +237,172 @@ __device__ __forceinline__ void fft_plane(float *sre, float *sim, int pol, int l
     passes16<G, 0>(sre, sim, pol, lt, tw, v);
 }
 
+// ------------------------------------------------- matrix-core radix 16 --
+//
+// A radix-16 pass as a dense product on the FP16 matrix cores
+// (v_mfma_f32_16x16x32_f16, FP32 accumulation).  One wave transforms 16
+// butterflies at a time: Y = W16 * X with the complex 16x16 DFT matrix in its
+// real 16x32 form, rows Re Y (operand ar) and Im Y (operand ai), columns
+// k = 2r + c for input point r and component c (0 = re, 1 = im):
+//   ar[m][2r] = Re W[m][r], ar[m][2r+1] = -Im W[m][r],
+//   ai[m][2r] = Im W[m][r], ai[m][2r+1] =  Re W[m][r].
+// Lane l holds butterfly n = l mod 16 and its input points 4(l/16)..+3 (the
+// B-operand layout of this instruction), so it can apply the pass twiddles
+// itself, and receives the outputs 4(l/16)..+3 of the same butterfly (the
+// accumulator layout).  Each butterfly's inputs are scaled by a power of two
+// that puts their largest component just below 2^15, then rounded to
+// FP16.  MFMA_FP16 uses single FP16 values of the matrix and of the data (one
+// product, relative rounding 2^-11 per operand); MFMA_FP16X2 splits both into
+// hi + lo pairs (x = hi + lo + O(2^-22 x)) and sums Wlo*hi + Whi*lo + Whi*hi.
+// The scale is undone exactly on the FP32 outputs.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct MfmaW {
+    half8 hr, hi, lr, li;   // hi and lo parts of the Re-row and Im-row operands
+};
+
+// Operands of lane `lane`, from W16^e = cos(pi e/8) - i sin(pi e/8) in double.
+__device__ __forceinline__ MfmaW mfma_dft16_operands(int lane) {
+    const int m = lane & 15, kb = lane >> 4;
+    MfmaW w;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int r = 4 * kb + (j >> 1);
+        const int e = (m * r) & 15;
+        double sn, cs;
+        sincospi((double)e / 8.0, &sn, &cs);
+        const double wr = cs, wi = -sn;
+        const double vr = (j & 1) ? -wi : wr;
+        const double vi = (j & 1) ? wr : wi;
+        const _Float16 hr = (_Float16)vr, hi = (_Float16)vi;
+        w.hr[j] = hr;
+        w.hi[j] = hi;
+        w.lr[j] = (_Float16)(vr - (double)hr);
+        w.li[j] = (_Float16)(vi - (double)hi);
+    }
+    return w;
+}
+
+// Radix-16 pass I as in pass16 (same inputs, twiddles and output positions),
+// on the matrix cores.  Every pass, the last included, writes its outputs to
+// LDS; the last one's land in natural order.  PREC 1: MFMA_FP16, 2: FP16X2.
+template <class G, int I, int PREC>
+__device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                            const MfmaW &W) {
+    constexpr int Ns = G::r0 * (1 << (4 * I));
+    constexpr int GR = 4;  // groups of 16 butterflies per wave
+    const int lane = lt & 63, wv = lt >> 6;
+    const int n = lane & 15, kb = lane >> 4;
+    float2 x[GR][4];
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+        const int b = wv * 64 + g * 16 + n;
+        const int c = b >> (G::logL - 4), bb = b & (G::L16 - 1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int a = G::idx(pol, c, bb + (4 * kb + t) * G::L16);
+            x[g][t] = make_float2(sre[a], sim[a]);
+        }
+        if (Ns > 1) {
+            const int k = bb & (Ns - 1);
+            const float2 *tk = tw + G::tw_off(I) + k * 15;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int r = 4 * kb + t;
+                if (r > 0) x[g][t] = cmul(x[g][t], tk[r - 1]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+        // per-butterfly power-of-two scale (lanes n, n+16, n+32, n+48)
+        float mx = fmaxf(fmaxf(fabsf(x[g][0].x), fabsf(x[g][0].y)), fabsf(x[g][1].x));
+        mx = fmaxf(fmaxf(mx, fabsf(x[g][1].y)), fabsf(x[g][2].x));
+        mx = fmaxf(fmaxf(mx, fabsf(x[g][2].y)), fabsf(x[g][3].x));
+        mx = fmaxf(mx, fabsf(x[g][3].y));
+        mx = fmaxf(mx, __shfl_xor(mx, 16));
+        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        const int sc = 15 - __builtin_amdgcn_frexp_expf(mx);
+        half8 bh, bl;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float xr = __builtin_amdgcn_ldexpf(x[g][t].x, sc);
+            const float xi = __builtin_amdgcn_ldexpf(x[g][t].y, sc);
+            const _Float16 hr = (_Float16)xr, hi = (_Float16)xi;
+            bh[2 * t] = hr;
+            bh[2 * t + 1] = hi;
+            if constexpr (PREC == 2) {
+                bl[2 * t] = (_Float16)(xr - (float)hr);
+                bl[2 * t + 1] = (_Float16)(xi - (float)hi);
+            }
+        }
+        floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == 2) {
+            // small terms first: Wlo*hi, Whi*lo, then Whi*hi
+            yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.lr, bh, yr, 0, 0, 0);
+            yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.li, bh, yi, 0, 0, 0);
+            yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.hr, bl, yr, 0, 0, 0);
+            yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.hi, bl, yi, 0, 0, 0);
+        }
+        yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.hr, bh, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.hi, bh, yi, 0, 0, 0);
+        const int b = wv * 64 + g * 16 + n;
+        const int c = b >> (G::logL - 4), bb = b & (G::L16 - 1);
+        const int k = bb & (Ns - 1);
+        const int base = ((bb - k) << 4) + k;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int a = G::idx(pol, c, base + (4 * kb + i) * Ns);
+            sre[a] = __builtin_amdgcn_ldexpf(yr[i], -sc);
+            sim[a] = __builtin_amdgcn_ldexpf(yi[i], -sc);
+        }
+    }
+    __syncthreads();
+}
+
+template <class G, int I, int PREC>
+__device__ __forceinline__ void passes16_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                              const MfmaW &W) {
+    pass16_mfma<G, I, PREC>(sre, sim, pol, lt, tw, W);
+    if constexpr (I + 1 < G::n16) passes16_mfma<G, I + 1, PREC>(sre, sim, pol, lt, tw, W);
+}
+
+// The batched FFT of fft_plane with its radix-16 passes on the matrix cores;
+// the result is left in LDS in natural order (column c, bin k at idx(pol, c,
+// k)) after a workgroup barrier.
+template <class G, int PREC>
+__device__ __forceinline__ void fft_plane_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                               const MfmaW &W) {
+    static_assert(G::TPP % 64 == 0, "whole waves per polarisation");
+    if constexpr (G::r0 > 1) pass_small<G, G::r0>(sre, sim, pol, lt);
+    passes16_mfma<G, 0, PREC>(sre, sim, pol, lt, tw, W);
+}
+
+// Precision dispatch: on return thread lt holds X_c[bb + r*L/16] in v (as
+// fft_plane), and with IN_LDS the whole transform is also in LDS in natural
+// order (matrix-core passes only).
+template <int PREC> struct FftPrec { static constexpr bool IN_LDS = PREC != 0; };
+
+template <class G, int PREC>
+__device__ __forceinline__ void fft_plane_p(float *sre, float *sim, int pol, int lt, const float2 *tw,
+                                            const MfmaW &W, float2 (&v)[16], bool want_regs) {
+    if constexpr (PREC == 0) {
+        fft_plane<G>(sre, sim, pol, lt, tw, v);
+    } else {
+        fft_plane_mfma<G, PREC>(sre, sim, pol, lt, tw, W);
+        if (want_regs) {
+            const int c = lt >> (G::logL - 4), bb = lt & (G::L16 - 1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int a = G::idx(pol, c, bb + r * G::L16);
+                v[r] = make_float2(sre[a], sim[a]);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- unpack --
 
 // One time sample: NPOL complex int8 values, two's complement, exact in float.

@@ -4,8 +4,8 @@
 
 namespace pfbs {
 
-hipError_t launch_front_single(const FrontArgs &a, int npol, bool pfb, int n_chunks, hipStream_t s);
-hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_items, hipStream_t s);
+hipError_t launch_front_single(const FrontArgs &a, int npol, bool pfb, int prec, int n_chunks, hipStream_t s);
+hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, int n_items, hipStream_t s);
 hipError_t init_single(int lds_limit);
 hipError_t init_fourstep(int lds_limit);
 
@@ -264,10 +264,10 @@ size_t front_lds_bytes(const Geo &g, int npol) {
 }
 size_t back_lds_bytes(const Geo &g, int npol) { return front_lds_bytes(g, npol); }
 
-hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_items,
+hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int prec, int n_items,
                         hipStream_t s) {
-    return single ? launch_front_single(a, npol, pfb, n_items, s)
-                  : launch_front_cols(a, npol, pfb, n_items, s);
+    return single ? launch_front_single(a, npol, pfb, prec, n_items, s)
+                  : launch_front_cols(a, npol, pfb, prec, n_items, s);
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s) {

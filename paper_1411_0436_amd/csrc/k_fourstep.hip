@@ -1,35 +1,47 @@
 // Two-pass (four-step) spectrometer kernels for 4096 < N <= 2^20: launch
-// wrappers around the bodies in fft_bodies.h.
+// wrappers around the bodies in fft_bodies.h, for the FP32 and the two
+// matrix-core precisions.
 #include "fft_bodies.h"
 
 namespace pfbs {
 
-template <int NPOL, bool PFB, int L>
-__global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_cols(FrontArgs a) {
-    front_cols_body<NPOL, PFB, L>(a, blockIdx.x, gridDim.x);
+// Minimum waves per SIMD that the column pass's register allocation must
+// allow: 4 caps a 512-thread workgroup at 128 VGPRs (two workgroups per CU,
+// which their LDS allows).  Measured per sub-FFT length and precision: the
+// cap pays where the uncapped kernel needs a little more than 128 registers
+// and costs where it forces large spills.
+template <int L, int PREC> struct ColsMinWaves {
+    static constexpr int value =
+        (PREC == 0 && L == 512) || (PREC == 1 && L == 128) || (PREC == 2 && (L == 128 || L == 256)) ? 4 : 1;
+};
+
+template <int NPOL, bool PFB, int L, int PREC>
+__global__ __launch_bounds__(kTilePoints / 16 * NPOL, (ColsMinWaves<L, PREC>::value)) void k_front_cols(FrontArgs a) {
+    front_cols_body<NPOL, PFB, L, PREC>(a, blockIdx.x, gridDim.x);
 }
 
-template <int NPOL, int L>
+template <int NPOL, int L, int PREC>
 __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a) {
-    back_body<NPOL, L>(a, blockIdx.x);
+    back_body<NPOL, L, PREC>(a, blockIdx.x);
 }
 
 #define PFBS_COLS_CASES(X) X(64) X(128) X(256) X(512)
 #define PFBS_BACK_CASES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
-hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_items, hipStream_t s) {
-    const size_t lds = front_lds_bytes(a.g, npol);
-    const dim3 grid(n_items * a.ntiles), block(kTilePoints / 16 * npol);
+namespace {
+template <int PREC>
+hipError_t launch_cols_p(const FrontArgs &a, int npol, bool pfb, dim3 grid, dim3 block, size_t lds,
+                         hipStream_t s) {
     switch (a.g.L) {
-#define PFBS_CASE(LL)                                                                           \
-    case LL:                                                                                    \
-        if (npol == 2) {                                                                        \
-            if (pfb) hipLaunchKernelGGL((k_front_cols<2, true, LL>), grid, block, lds, s, a);   \
-            else hipLaunchKernelGGL((k_front_cols<2, false, LL>), grid, block, lds, s, a);      \
-        } else {                                                                                \
-            if (pfb) hipLaunchKernelGGL((k_front_cols<1, true, LL>), grid, block, lds, s, a);   \
-            else hipLaunchKernelGGL((k_front_cols<1, false, LL>), grid, block, lds, s, a);      \
-        }                                                                                       \
+#define PFBS_CASE(LL)                                                                               \
+    case LL:                                                                                        \
+        if (npol == 2) {                                                                            \
+            if (pfb) hipLaunchKernelGGL((k_front_cols<2, true, LL, PREC>), grid, block, lds, s, a); \
+            else hipLaunchKernelGGL((k_front_cols<2, false, LL, PREC>), grid, block, lds, s, a);    \
+        } else {                                                                                    \
+            if (pfb) hipLaunchKernelGGL((k_front_cols<1, true, LL, PREC>), grid, block, lds, s, a); \
+            else hipLaunchKernelGGL((k_front_cols<1, false, LL, PREC>), grid, block, lds, s, a);    \
+        }                                                                                           \
         break;
         PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
@@ -39,14 +51,13 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int n_items
     return hipGetLastError();
 }
 
-hipError_t launch_back(const BackArgs &a, int npol, int n_chunks, hipStream_t s) {
-    const size_t lds = back_lds_bytes(a.g, npol);
-    const dim3 grid(n_chunks * a.ntiles), block(a.g.T * a.g.L / 16 * npol);
+template <int PREC>
+hipError_t launch_back_p(const BackArgs &a, int npol, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
     switch (a.g.L) {
-#define PFBS_CASE(LL)                                                              \
-    case LL:                                                                       \
-        if (npol == 2) hipLaunchKernelGGL((k_back<2, LL>), grid, block, lds, s, a); \
-        else hipLaunchKernelGGL((k_back<1, LL>), grid, block, lds, s, a);           \
+#define PFBS_CASE(LL)                                                                     \
+    case LL:                                                                              \
+        if (npol == 2) hipLaunchKernelGGL((k_back<2, LL, PREC>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((k_back<1, LL, PREC>), grid, block, lds, s, a);           \
         break;
         PFBS_BACK_CASES(PFBS_CASE)
 #undef PFBS_CASE
@@ -56,7 +67,8 @@ hipError_t launch_back(const BackArgs &a, int npol, int n_chunks, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t init_fourstep(int lds_limit) {
+template <int PREC>
+hipError_t init_fourstep_p(int lds_limit) {
     hipError_t e = hipSuccess;
 #define PFBS_ATTR(fn)                                                                            \
     do {                                                                                         \
@@ -64,18 +76,47 @@ hipError_t init_fourstep(int lds_limit) {
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit); \
         if (r != hipSuccess) e = r;                                                              \
     } while (0);
-#define PFBS_CASE(LL)                        \
-    PFBS_ATTR((k_front_cols<2, true, LL>))   \
-    PFBS_ATTR((k_front_cols<2, false, LL>))  \
-    PFBS_ATTR((k_front_cols<1, true, LL>))   \
-    PFBS_ATTR((k_front_cols<1, false, LL>))
+#define PFBS_CASE(LL)                              \
+    PFBS_ATTR((k_front_cols<2, true, LL, PREC>))   \
+    PFBS_ATTR((k_front_cols<2, false, LL, PREC>))  \
+    PFBS_ATTR((k_front_cols<1, true, LL, PREC>))   \
+    PFBS_ATTR((k_front_cols<1, false, LL, PREC>))
     PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
-#define PFBS_CASE(LL) PFBS_ATTR((k_back<2, LL>)) PFBS_ATTR((k_back<1, LL>))
+#define PFBS_CASE(LL) PFBS_ATTR((k_back<2, LL, PREC>)) PFBS_ATTR((k_back<1, LL, PREC>))
     PFBS_BACK_CASES(PFBS_CASE)
 #undef PFBS_CASE
 #undef PFBS_ATTR
     return e;
+}
+}  // namespace
+
+hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, int n_items, hipStream_t s) {
+    const size_t lds = front_lds_bytes(a.g, npol);
+    const dim3 grid(n_items * a.ntiles), block(kTilePoints / 16 * npol);
+    switch (prec) {
+    case 0: return launch_cols_p<0>(a, npol, pfb, grid, block, lds, s);
+    case 1: return launch_cols_p<1>(a, npol, pfb, grid, block, lds, s);
+    case 2: return launch_cols_p<2>(a, npol, pfb, grid, block, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s) {
+    const size_t lds = back_lds_bytes(a.g, npol);
+    const dim3 grid(n_chunks * a.ntiles), block(a.g.T * a.g.L / 16 * npol);
+    switch (prec) {
+    case 0: return launch_back_p<0>(a, npol, grid, block, lds, s);
+    case 1: return launch_back_p<1>(a, npol, grid, block, lds, s);
+    case 2: return launch_back_p<2>(a, npol, grid, block, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t init_fourstep(int lds_limit) {
+    hipError_t e0 = init_fourstep_p<0>(lds_limit), e1 = init_fourstep_p<1>(lds_limit),
+               e2 = init_fourstep_p<2>(lds_limit);
+    return e0 != hipSuccess ? e0 : (e1 != hipSuccess ? e1 : e2);
 }
 
 }  // namespace pfbs

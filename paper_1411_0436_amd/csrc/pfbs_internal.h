@@ -135,9 +135,10 @@ hipError_t launch_tables_taps(float *h, long long N, int P, int window, const do
                               hipStream_t s);
 hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s);
 hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_t s);
-hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int n_items,
+// prec: 0 = FP32, 1 = matrix cores with an FP16 DFT matrix, 2 = hi + lo matrix
+hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int prec, int n_items,
                         hipStream_t s);
-hipError_t launch_back(const BackArgs &a, int npol, int n_chunks, hipStream_t s);
+hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s);
 hipError_t launch_history(uint8_t *dst, const Frames &fr, long long F, int H, long long frame_bytes,
                           hipStream_t s);

@@ -309,8 +309,6 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
         if (st != PFBS_OK) return st;
     }
     const pfbs_plan_desc *desc = &tuned;
-    if (desc->precision != PFBS_PREC_FP32)
-        return fail(PFBS_ERR_UNSUPPORTED, "precision %d is not available in this build", desc->precision);
 
     int dev = desc->device;
     if (dev < 0) {
@@ -650,11 +648,11 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
 pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s) {
     if (w.any) {
         if (!p->fourstep) {
-            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(w.single, p->npol, p->pfb, true, w.single_chunks, s); }));
+            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(w.single, p->npol, p->pfb, true, p->precision, w.single_chunks, s); }));
         } else {
             for (const Group &g : w.groups) {
-                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(g.fa, p->npol, p->pfb, false, g.na, s); }));
-                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(g.ba, p->npol, g.nc, s); }));
+                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(g.fa, p->npol, p->pfb, false, p->precision, g.na, s); }));
+                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(g.ba, p->npol, p->precision, g.nc, s); }));
             }
         }
         PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(w.ra, w.n_dumps, s); }));

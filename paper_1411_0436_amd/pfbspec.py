@@ -69,6 +69,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libpfbspec.so not built (%s); run __graft_entry__.build()" % path)
+    # PyTorch ships its own HIP runtime under the same soname; loading it
+    # first makes the library bind to that one runtime instead of bringing a
+    # second one into the process (two runtimes do not share the device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     pi64 = ctypes.POINTER(ctypes.c_int64)

@@ -1,0 +1,145 @@
+"""Short text summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_1411_0436_amd.prof_summary stats KERNEL_STATS_CSV OUT --command "..."
+        per-kernel calls / average / total time of a --kernel-trace --stats run;
+
+    python -m paper_1411_0436_amd.prof_summary traffic --fetch DIR --write DIR
+        --copy-fetch DIR --copy-write DIR --match NAME --kind KIND
+        --workload W --precision P OUT --command "..."
+        HBM bytes per dispatch of the kernels whose name contains NAME, from a
+        FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled by
+        what the same counter reads for a plain device copy of known size
+        (bytes moved / counter bytes).  The summary records the digest of the
+        kernel sources so that a later change of the kernels retires it.
+
+Only rocprofv3's CSV files are read; nothing here touches the GPU.
+"""
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["fft_common.h", "fft_bodies.h", "k_single.hip", "k_fourstep.hip", "pfbs_internal.h"]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter, match):
+    """Average over dispatches of the summed counter (over its instances) for
+    kernels whose name contains `match`; also returns the dispatch count."""
+    per = collections.defaultdict(float)
+    names = {}
+    for r in rows:
+        if r["Counter_Name"] != counter or match not in r["Kernel_Name"]:
+            continue
+        per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        names[r["Dispatch_Id"]] = r["Kernel_Name"]
+    if not per:
+        raise SystemExit("no %s rows for kernels matching %r" % (counter, match))
+    return sum(per.values()) / len(per), len(per), sorted(set(names.values()))
+
+
+def _copy_factor(rows, counter, copy_bytes):
+    # the largest dispatch of the calibration run is the device copy
+    best = 0.0
+    for r in rows:
+        if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]:
+            best = max(best, float(r["Counter_Value"]))
+    if best <= 0:
+        raise SystemExit("no copy dispatch with %s in the calibration run" % counter)
+    return copy_bytes / (best * 1024.0), best
+
+
+def cmd_stats(a):
+    with open(a.csv) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["# rocprofv3 --kernel-trace --stats summary", "# command: %s" % a.command,
+           "# kernel sources sha1: %s" % kernel_digest(), "",
+           "%-64s %7s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_ms", "share")]
+    for r in rows[: a.top]:
+        name = r["Name"].replace("void ", "").split("(")[0]
+        out.append("%-64s %7s %12.2f %12.3f %6.1f%%" % (name[:64], r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                       float(r["TotalDurationNs"]) / 1e6,
+                                                       100.0 * float(r["TotalDurationNs"]) / tot))
+    _write(a.out, out)
+
+
+def cmd_traffic(a):
+    fr, wr = _counter_rows(a.fetch), _counter_rows(a.write)
+    cf, cw = _counter_rows(a.copy_fetch), _counter_rows(a.copy_write)
+    copy_bytes = a.copy_mib * 1048576.0
+    kf, cf_raw = _copy_factor(cf, "FETCH_SIZE", copy_bytes)
+    kw, cw_raw = _copy_factor(cw, "WRITE_SIZE", copy_bytes)
+    f_kib, nf, names = _per_dispatch(fr, "FETCH_SIZE", a.match)
+    w_kib, nw, _ = _per_dispatch(wr, "WRITE_SIZE", a.match)
+    out = ["# HBM traffic per dispatch from rocprofv3 counters", "# commands: %s" % a.command,
+           "# kernels: %s" % "; ".join(n.replace("void ", "").split("(")[0] for n in names),
+           "# copy calibration: %.0f MiB device copy reads FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB"
+           % (a.copy_mib, cf_raw, cw_raw),
+           "kernel: %s" % a.kind, "workload: %s" % a.workload, "precision: %s" % a.precision,
+           "kernel_sources_sha1: %s" % kernel_digest(),
+           "dispatches: %d fetch, %d write" % (nf, nw),
+           "fetch_kib_per_dispatch: %.1f" % f_kib, "write_kib_per_dispatch: %.1f" % w_kib,
+           "fetch_scale: %.4f" % kf, "write_scale: %.4f" % kw,
+           "fetch_bytes_per_launch: %.0f" % (f_kib * 1024.0 * kf),
+           "write_bytes_per_launch: %.0f" % (w_kib * 1024.0 * kw)]
+    _write(a.out, out)
+
+
+def _write(path, lines):
+    text = "\n".join(lines) + "\n"
+    if path == "-":
+        sys.stdout.write(text)
+    else:
+        with open(path, "w") as fh:
+            fh.write(text)
+        sys.stdout.write(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=20)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--copy-mib", type=float, default=1024.0)
+    t.add_argument("--match", required=True)
+    t.add_argument("--kind", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--precision", default="fp32")
+    t.add_argument("--command", required=True)
+    t.add_argument("out")
+    a = ap.parse_args(argv)
+    (cmd_stats if a.cmd == "stats" else cmd_traffic)(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -28,7 +28,10 @@ def rel_err(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
 U32 = 2.0 ** -24
 
 
-def fp32_bound(ref: np.ndarray, N: int, c: float = 8.0) -> np.ndarray:
+U16 = 2.0 ** -11
+
+
+def fp32_bound(ref: np.ndarray, N: int, c: float = 8.0, u: float = U32) -> np.ndarray:
     """Per-channel error bound of integrated products from FP32 arithmetic.
 
     A floating-point FFT has a normwise error |dX_jk| <= c*u*sqrt(log2 N)*rms_j
@@ -45,12 +48,13 @@ def fp32_bound(ref: np.ndarray, N: int, c: float = 8.0) -> np.ndarray:
         sc = np.sqrt(ref[0] * ref[1])
         scale = np.stack([ref[0], ref[1], sc, sc])
     mean = scale.mean(axis=1, keepdims=True)
-    return 1e-5 * scale + 2 * c * U32 * np.sqrt(np.log2(N)) * np.sqrt(scale * mean)
+    return 1e-5 * scale + 2 * c * u * np.sqrt(np.log2(N)) * np.sqrt(scale * mean)
 
 
-def within_fp32_bound(got, ref, N) -> float:
-    """max over channels of |got - ref| / bound (<= 1 passes)."""
-    return float(np.max(np.abs(np.asarray(got, np.float64) - ref) / fp32_bound(ref, N)))
+def within_fp32_bound(got, ref, N, u: float = U32, c: float = 8.0) -> float:
+    """max over channels of |got - ref| / bound (<= 1 passes).  ``u`` is the
+    unit roundoff of the arithmetic (2^-24 for FP32, 2^-11 for FP16)."""
+    return float(np.max(np.abs(np.asarray(got, np.float64) - ref) / fp32_bound(ref, N, c=c, u=u)))
 
 
 def run_stream(plan, x: np.ndarray, block_frames, keep_device=False):

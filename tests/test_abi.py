@@ -100,3 +100,19 @@ def test_no_device_gives_device_error_not_crash():
     st, h = _create(N=1024, P=8, n_int=4)
     assert st in (pf.ERR_DEVICE, pf.ERR_NOMEM, pf.ERR_UNSUPPORTED)
     assert not h.value
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library must not bring a second HIP runtime into a process
+    that uses PyTorch: the library binds libamdhip64 by soname to the copy
+    PyTorch loaded (two runtimes in one process do not share the device)."""
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1411_0436_amd import pfbspec as pf\n"
+            "pf.load()\n"
+            "import re\n"
+            "print(sorted(set(re.findall(r'/\\S*libamdhip64\\S*', open('/proc/self/maps').read()))))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr
+    paths = eval(out.stdout.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
