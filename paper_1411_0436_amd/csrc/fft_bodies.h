@@ -17,7 +17,7 @@ namespace pfbs {
 template <int NPOL, bool PFB, int L, int PREC = 0>
 __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
     typedef Geom<L> G;
-    typedef typename Sample<NPOL>::word W;
+    typedef typename Sample<NPOL>::word4 W4;
     constexpr int NB = G::TPP * NPOL;      // threads
     constexpr int PTS = kTilePoints / NB;  // pre-filter points per thread (all pols each)
     constexpr int NP = NPOL == 2 ? 4 : 1;  // products
@@ -48,32 +48,39 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
         for (int s = 0; s < PTS; ++s)
 #pragma unroll
             for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
+        // work item q: four consecutive points 4q .. 4q+3 of the T columns
         for (int p = 0; p < P; ++p) {
 #pragma unroll
-            for (int s = 0; s < PTS; ++s) {
-                const int i = tid + NB * s;
+            for (int g = 0; g < PTS / 4; ++g) {
+                const int i = 4 * (tid + NB * g);
                 const int c = i >> G::logL, n = i & (L - 1);
                 const long long jj = j0 + c;
                 if (jj < je) {
-                    const W w = frame_ptr<NPOL>(a.fr, jj + p, L)[n];
+                    const W4 w4 = *reinterpret_cast<const W4 *>(frame_ptr<NPOL>(a.fr, jj + p, L) + n);
                     if (PFB) {
-                        tap_fma<NPOL>(y[s], a.taps[p * L + n], w);
+                        const float4 h4 = *reinterpret_cast<const float4 *>(a.taps + p * L + n);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            tap_fma<NPOL>(y[4 * g + e], part4(h4, e), Sample<NPOL>::part(w4, e));
                     } else {
-                        Sample<NPOL>::unpack(w, y[s]);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4, e), y[4 * g + e]);
                     }
                 }
             }
         }
 #pragma unroll
-        for (int s = 0; s < PTS; ++s) {
-            const int i = tid + NB * s;
+        for (int g = 0; g < PTS / 4; ++g) {
+            const int i = 4 * (tid + NB * g);
             const int c = i >> G::logL, n = i & (L - 1);
 #pragma unroll
-            for (int pp = 0; pp < NPOL; ++pp) {
-                const int ad = G::idx(pp, c, n);
-                sre[ad] = y[s][pp].x;
-                sim[ad] = y[s][pp].y;
-            }
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int pp = 0; pp < NPOL; ++pp) {
+                    const int ad = G::idx(pp, c, n + e);
+                    sre[ad] = y[4 * g + e][pp].x;
+                    sim[ad] = y[4 * g + e][pp].y;
+                }
         }
         __syncthreads();
         float2 v[16];
@@ -148,7 +155,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
     constexpr int NB = G::TPP * NPOL;
-    constexpr int PTS = kTilePoints / NB;
+    constexpr int PTS = G::TP / NB;
     extern __shared__ float smem[];
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
@@ -181,6 +188,10 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     MfmaW Wm{};
     if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
 
+    // pre-filter work item q: four consecutive columns 4*(q mod T/4) .. +3 of
+    // row n2 = q / (T/4), read with one 16-byte access per frame and per tap row
+    static_assert(G::T % 4 == 0 && PTS % 4 == 0, "column tile of whole 4-sample groups");
+    typedef typename Sample<NPOL>::word4 W4;
     for (long long j = js; j < je; ++j) {
         float2 y[PTS][NPOL];
 #pragma unroll
@@ -192,24 +203,32 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
             const W *fb = frame_ptr<NPOL>(a.fr, j + p, N) + n1_0;
             const float *hb = a.taps + (long long)p * N + n1_0;
 #pragma unroll
-            for (int s = 0; s < PTS; ++s) {
-                const int i = tid + NB * s;
-                const unsigned n = (unsigned)((i & (G::T - 1)) + N1 * (i >> G::logT));
-                const W w = fb[n];
-                if (PFB) tap_fma<NPOL>(y[s], hb[n], w);
-                else Sample<NPOL>::unpack(w, y[s]);
+            for (int g = 0; g < PTS / 4; ++g) {
+                const int q = tid + NB * g;
+                const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
+                const W4 w4 = *reinterpret_cast<const W4 *>(fb + n);
+                if (PFB) {
+                    const float4 h4 = *reinterpret_cast<const float4 *>(hb + n);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) tap_fma<NPOL>(y[4 * g + e], part4(h4, e), Sample<NPOL>::part(w4, e));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4, e), y[4 * g + e]);
+                }
             }
         }
 #pragma unroll
-        for (int s = 0; s < PTS; ++s) {
-            const int i = tid + NB * s;
-            const int c = i & (G::T - 1), n2 = i >> G::logT;
+        for (int g = 0; g < PTS / 4; ++g) {
+            const int q = tid + NB * g;
+            const int c0 = 4 * (q & (G::T / 4 - 1)), n2 = q >> (G::logT - 2);
 #pragma unroll
-            for (int pp = 0; pp < NPOL; ++pp) {
-                const int ad = G::idx(pp, c, n2);
-                sre[ad] = y[s][pp].x;
-                sim[ad] = y[s][pp].y;
-            }
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int pp = 0; pp < NPOL; ++pp) {
+                    const int ad = G::idx(pp, c0 + e, n2);
+                    sre[ad] = y[4 * g + e][pp].x;
+                    sim[ad] = y[4 * g + e][pp].y;
+                }
         }
         __syncthreads();
         float2 v[16];
@@ -225,24 +244,20 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
             sim[ad] = z.y;
         }
         __syncthreads();
-        // ---- coalesced store: T consecutive n1 of each (pol, k2) row
+        // ---- coalesced store: T consecutive n1 of each (pol, k2) row, two
+        // complex values (16 bytes) per access
         float2 *zb = a.Z + (j - a.jz0) * NPOL * N + n1_0;
 #pragma unroll
-        for (int s = 0; s < (NPOL * kTilePoints) / NB; ++s) {
+        for (int s = 0; s < (NPOL * G::TP) / (2 * NB); ++s) {
             const int i = tid + NB * s;
-            const int cc = i & (G::T - 1);
-            const int k2 = (i >> G::logT) & (L - 1);
-            const int pp = i >> (G::logT + G::logL);
-            const int ad = G::idx(pp, cc, k2);
-            float2 *zp = zb + (unsigned)(pp * (int)N + k2 * N1 + cc);
-            if (a.znt) {
-                // streaming store: Z is read once, by the row pass
-                float *zf = reinterpret_cast<float *>(zp);
-                __builtin_nontemporal_store(sre[ad], zf);
-                __builtin_nontemporal_store(sim[ad], zf + 1);
-            } else {
-                *zp = make_float2(sre[ad], sim[ad]);
-            }
+            const int cc = 2 * (i & (G::T / 2 - 1));
+            const int k2 = (i >> (G::logT - 1)) & (L - 1);
+            const int pp = i >> (G::logT - 1 + G::logL);
+            const int ad0 = G::idx(pp, cc, k2), ad1 = G::idx(pp, cc + 1, k2);
+            const floatx4 v = {sre[ad0], sim[ad0], sre[ad1], sim[ad1]};
+            floatx4 *zp = reinterpret_cast<floatx4 *>(zb + (unsigned)(pp * (int)N + k2 * N1 + cc));
+            if (a.znt) __builtin_nontemporal_store(v, zp);  // Z is read once, by the row pass
+            else *zp = v;
         }
         __syncthreads();
     }
@@ -280,22 +295,43 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
 
     for (long long j = js; j < je; ++j) {
         const float2 *zb = a.Z + (j - a.jz0) * NPOL * N + (long long)k2_0 * L;
+        if constexpr (L >= 1024) {
+            // one complex value per access: consecutive lanes write
+            // consecutive LDS words (the paired form below halves the
+            // accesses but doubles the LDS bank conflicts of long rows)
 #pragma unroll
-        for (int s = 0; s < (NPOL * G::TP) / NB; ++s) {
-            const int i = tid + NB * s;
-            const int n1 = i & (L - 1);
-            const int cc = (i >> G::logL) & (G::T - 1);
-            const int pp = i >> (G::logL + G::logT);
-            const float2 *zp = zb + (unsigned)(pp * (int)N + cc * L + n1);
-            const int ad = G::idx(pp, cc, n1);
-            if (a.znt) {
-                const float *zf = reinterpret_cast<const float *>(zp);
-                sre[ad] = __builtin_nontemporal_load(zf);
-                sim[ad] = __builtin_nontemporal_load(zf + 1);
-            } else {
-                const float2 z = *zp;
-                sre[ad] = z.x;
-                sim[ad] = z.y;
+            for (int s = 0; s < (NPOL * G::TP) / NB; ++s) {
+                const int i = tid + NB * s;
+                const int n1 = i & (L - 1);
+                const int cc = (i >> G::logL) & (G::T - 1);
+                const int pp = i >> (G::logL + G::logT);
+                const float2 *zp = zb + (unsigned)(pp * (int)N + cc * L + n1);
+                const int ad = G::idx(pp, cc, n1);
+                if (a.znt) {
+                    const float *zf = reinterpret_cast<const float *>(zp);
+                    sre[ad] = __builtin_nontemporal_load(zf);
+                    sim[ad] = __builtin_nontemporal_load(zf + 1);
+                } else {
+                    const float2 z = *zp;
+                    sre[ad] = z.x;
+                    sim[ad] = z.y;
+                }
+            }
+        } else {
+            // two consecutive n1 (16 bytes) per access
+#pragma unroll
+            for (int s = 0; s < (NPOL * G::TP) / (2 * NB); ++s) {
+                const int i = tid + NB * s;
+                const int n1 = 2 * (i & (L / 2 - 1));
+                const int cc = (i >> (G::logL - 1)) & (G::T - 1);
+                const int pp = i >> (G::logL - 1 + G::logT);
+                const floatx4 *zp = reinterpret_cast<const floatx4 *>(zb + (unsigned)(pp * (int)N + cc * L + n1));
+                const floatx4 z = a.znt ? __builtin_nontemporal_load(zp) : *zp;
+                const int ad0 = G::idx(pp, cc, n1), ad1 = G::idx(pp, cc, n1 + 1);
+                sre[ad0] = z[0];
+                sim[ad0] = z[1];
+                sre[ad1] = z[2];
+                sim[ad1] = z[3];
             }
         }
         __syncthreads();

@@ -407,19 +407,34 @@ __device__ __forceinline__ void fft_plane_p(float *sre, float *sim, int pol, int
 
 // One time sample: NPOL complex int8 values, two's complement, exact in float.
 template <int NPOL> struct Sample;
+// word4: four consecutive time samples, loaded with one 16-byte (dual) or
+// 8-byte (single polarisation) access.
 template <> struct Sample<2> {
     typedef uint32_t word;
+    typedef uint4 word4;
     __device__ __forceinline__ static void unpack(word w, float2 (&x)[2]) {
         x[0] = make_float2((float)(int8_t)(w & 0xff), (float)(int8_t)((w >> 8) & 0xff));
         x[1] = make_float2((float)(int8_t)((w >> 16) & 0xff), (float)(int8_t)(w >> 24));
     }
+    __device__ __forceinline__ static word part(const word4 &v, int e) {
+        return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+    }
 };
 template <> struct Sample<1> {
     typedef uint16_t word;
+    typedef uint2 word4;
     __device__ __forceinline__ static void unpack(word w, float2 (&x)[1]) {
         x[0] = make_float2((float)(int8_t)(w & 0xff), (float)(int8_t)(w >> 8));
     }
+    __device__ __forceinline__ static word part(const word4 &v, int e) {
+        const uint32_t d = e < 2 ? v.x : v.y;
+        return (word)((e & 1) ? (d >> 16) : (d & 0xffff));
+    }
 };
+
+__device__ __forceinline__ float part4(const float4 &v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
 
 // Base address of frame f (block if f >= fs, else tap history).
 template <int NPOL>
