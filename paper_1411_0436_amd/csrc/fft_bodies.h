@@ -162,14 +162,21 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
     // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
     // contiguous range of tiles and walk each tile's spectra consecutively, so
-    // the workgroups that share an L2 share taps and frames.
+    // the workgroups that share an L2 share taps and frames.  Tiles whose int8
+    // row segments are narrower than a 128-byte line run as a group of TG
+    // adjacent tiles that together fill the line, spectrum by spectrum.
     int tile, item;
     {
         const int nitems = nblk / a.ntiles;
         if ((a.ntiles & 7) == 0) {
+            constexpr int SEG = G::T * 2 * NPOL;              // bytes of a tile's row segment
+            constexpr int TGW = SEG >= 128 ? 1 : 128 / SEG;
+            const int tpx = a.ntiles >> 3;
+            const int TG = tpx % TGW == 0 ? TGW : 1;
             const int xcd = bid & 7, local = bid >> 3;
-            tile = xcd * (a.ntiles >> 3) + local / nitems;
-            item = local % nitems;
+            const int grp = local / (TG * nitems), rem = local - grp * (TG * nitems);
+            tile = xcd * tpx + grp * TG + rem % TG;
+            item = rem / TG;
         } else {
             tile = bid % a.ntiles;
             item = bid / a.ntiles;
