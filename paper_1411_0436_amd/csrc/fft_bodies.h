@@ -172,7 +172,8 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
             constexpr int SEG = G::T * 2 * NPOL;              // bytes of a tile's row segment
             constexpr int TGW = SEG >= 128 ? 1 : 128 / SEG;
             const int tpx = a.ntiles >> 3;
-            const int TG = tpx % TGW == 0 ? TGW : 1;
+            int TG = TGW;
+            while (tpx % TG) TG >>= 1;
             const int xcd = bid & 7, local = bid >> 3;
             const int grp = local / (TG * nitems), rem = local - grp * (TG * nitems);
             tile = xcd * tpx + grp * TG + rem % TG;
