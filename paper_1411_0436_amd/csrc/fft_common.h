@@ -136,7 +136,7 @@ struct Geom {
     static constexpr int n16 = logL / 4;
     static constexpr int r0 = 1 << (logL % 4);
     static constexpr int L16 = L / 16;
-    static constexpr int Lp = L + L / 16 + 1;
+    static constexpr int Lp = lds_pitch(L);
     static constexpr int plane = T * Lp;  // floats of one polarisation plane
     static_assert(T >= 1 && L >= 16, "sub-FFT geometry");
     __device__ __forceinline__ static int idx(int pol, int c, int e) {

@@ -259,7 +259,7 @@ hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_
 }
 
 size_t front_lds_bytes(const Geo &g, int npol) {
-    const size_t Lp = (size_t)g.L + g.L / 16 + 1;
+    const size_t Lp = (size_t)lds_pitch(g.L);
     return (size_t)2 * npol * g.T * Lp * sizeof(float);
 }
 size_t back_lds_bytes(const Geo &g, int npol) { return front_lds_bytes(g, npol); }

@@ -10,6 +10,11 @@ namespace pfbs {
 constexpr int kTilePoints = 4096;    // T * L: complex points per polarisation per workgroup step
 constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
 
+// LDS words per column of an L-point sub-FFT plane: one pad word per 16
+// elements and one more per column (pads of 0, 3 and 9 words per column
+// measured no better).
+constexpr int lds_pitch(int L) { return L + L / 16 + 1; }
+
 // Runtime view of the batched sub-FFT geometry (the kernels take L as a
 // template parameter; the host keeps these facts and the twiddle table).
 struct Geo {
