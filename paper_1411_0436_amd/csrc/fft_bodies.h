@@ -150,6 +150,31 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
 //   rows of Z), the polarisation products and their accumulation in registers
 //   over the spectra of a chunk; the chunk's sums are written at
 //   u = k2*N1 + k1 (the reduction restores channel order).
+// Column-pass workgroup -> (column tile, run of spectra).  Workgroups are
+// dealt to the 8 XCDs round-robin; give each XCD a contiguous range of tiles
+// and walk each tile's spectra consecutively, so the workgroups that share an
+// L2 share taps and frames.  Tiles whose int8 row segments are narrower than
+// a 128-byte line run as a group of TG adjacent tiles that together fill the
+// line, spectrum by spectrum.
+template <int T, int NPOL>
+__device__ __forceinline__ void cols_tile_item(int ntiles, int bid, int nblk, int &tile, int &item) {
+    const int nitems = nblk / ntiles;
+    if ((ntiles & 7) == 0) {
+        constexpr int SEG = T * 2 * NPOL;  // bytes of a tile's row segment
+        constexpr int TGW = SEG >= 128 ? 1 : 128 / SEG;
+        const int tpx = ntiles >> 3;
+        int TG = TGW;
+        while (tpx % TG) TG >>= 1;
+        const int xcd = bid & 7, local = bid >> 3;
+        const int grp = local / (TG * nitems), rem = local - grp * (TG * nitems);
+        tile = xcd * tpx + grp * TG + rem % TG;
+        item = rem / TG;
+    } else {
+        tile = bid % ntiles;
+        item = bid / ntiles;
+    }
+}
+
 template <int NPOL, bool PFB, int L, int PREC = 0>
 __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int nblk) {
     typedef Geom<L> G;
@@ -160,29 +185,8 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
     const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
-    // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-    // contiguous range of tiles and walk each tile's spectra consecutively, so
-    // the workgroups that share an L2 share taps and frames.  Tiles whose int8
-    // row segments are narrower than a 128-byte line run as a group of TG
-    // adjacent tiles that together fill the line, spectrum by spectrum.
     int tile, item;
-    {
-        const int nitems = nblk / a.ntiles;
-        if ((a.ntiles & 7) == 0) {
-            constexpr int SEG = G::T * 2 * NPOL;              // bytes of a tile's row segment
-            constexpr int TGW = SEG >= 128 ? 1 : 128 / SEG;
-            const int tpx = a.ntiles >> 3;
-            int TG = TGW;
-            while (tpx % TG) TG >>= 1;
-            const int xcd = bid & 7, local = bid >> 3;
-            const int grp = local / (TG * nitems), rem = local - grp * (TG * nitems);
-            tile = xcd * tpx + grp * TG + rem % TG;
-            item = rem / TG;
-        } else {
-            tile = bid % a.ntiles;
-            item = bid / a.ntiles;
-        }
-    }
+    cols_tile_item<G::T, NPOL>(a.ntiles, bid, nblk, tile, item);
     // spectra [js, je): the item-th run of ga spectra of the launch's range
     const long long js = a.sa0 + (long long)item * a.ga;
     const long long je = min(js + (long long)a.ga, a.sa1);

@@ -368,9 +368,6 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->frame_bytes = p->N * 2 * p->npol;
     p->ga_force = desc->col_run;
     p->znt = desc->stream_z;
-    // environment overrides, for measurement sweeps
-    if (const char *e = getenv("PFBS_GA")) p->ga_force = atoi(e);
-    if (const char *e = getenv("PFBS_ZNT")) p->znt = atoi(e);
 
     hipStream_t s = nullptr;
     double *d_custom = nullptr;
