@@ -96,7 +96,7 @@ std::vector<int64_t> splits_for(int64_t N) {
     for (int64_t n2 = 64; n2 <= 512; n2 *= 2) {
         const int64_t n1 = N / n2;
         if (n1 < 32 || n1 > pfbs::kMaxSinglePass) continue;
-        const int tb = n1 < 1024 ? 1024 : (int)n1;
+        const int tb = pfbs::back_tile_points(n1);
         if (n1 % (pfbs::kTilePoints / n2) == 0 && n2 % (tb / n1) == 0) v.push_back(n2);
     }
     return v;

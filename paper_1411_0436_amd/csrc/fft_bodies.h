@@ -277,7 +277,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 
 // Row-pass tile: at least 1024 points per polarisation (64 threads each), so
 // short rows still give many small workgroups.
-template <int L> struct BackTile { static constexpr int TP = L < 1024 ? 1024 : L; };
+template <int L> struct BackTile { static constexpr int TP = back_tile_points(L); };
 
 template <int NPOL, int L, int PREC = 0>
 __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {

@@ -10,6 +10,10 @@ namespace pfbs {
 constexpr int kTilePoints = 4096;    // T * L: complex points per polarisation per workgroup step
 constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
 
+// Points per polarisation per workgroup step of the row pass: whole rows, at
+// least 1024 (whole waves per polarisation; 2048 measured slower).
+constexpr int back_tile_points(long long n1) { return n1 < 1024 ? 1024 : (int)n1; }
+
 // LDS words per column of an L-point sub-FFT plane: one pad word per 16
 // elements and one more per column (pads of 0, 3 and 9 words per column
 // measured no better).

@@ -161,7 +161,7 @@ pfbs_status hip_fail(pfbs_plan *p, hipError_t e, const char *what) {
 
 // Column length N2 (pass A) and row length N1 = N/N2 (pass B) of the
 // two-pass FFT: both must have kernels built for them and tile evenly.
-int back_tile(int64_t n1) { return n1 < 1024 ? 1024 : (int)n1; }  // row-pass points per pol
+int back_tile(int64_t n1) { return back_tile_points(n1); }  // row-pass points per pol
 
 bool split_ok(int64_t N, int64_t n2) {
     if (!is_pow2(n2) || n2 < 64 || n2 > 512) return false;
