@@ -45,7 +45,7 @@ WORKLOADS = {
     "c4-65536": dict(N=65536, P=8, direct=False, n_pol=2, n_int=1024, block=1 << 24, blocks=8, spec="c2"),
     "c4-524288": dict(N=1 << 19, P=8, direct=False, n_pol=2, n_int=128, block=1 << 24, blocks=8, spec="c2"),
 }
-PRECISIONS = {"fp32": 0, "fp16": 1, "fp16x2": 2}
+PRECISIONS = {"fp32": 0, "fp16": 1, "fp16x2": 2, "mixed": 3}
 
 # Sources that define the spectrometer kernels: a traffic summary under
 # profiles/ applies only while their digest is unchanged.
@@ -339,7 +339,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "fp16x2": "f16x2 (f32 accumulate)"}[args.precision],
+        "dtype": {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "fp16x2": "f16x2 (f32 accumulate)",
+                  "mixed": "f32 columns, f16x2 rows (f32 accumulate)"}[args.precision],
         "data": "synthetic (seeded int8 noise + tones, device-resident blocks)",
         "config": {"workload": args.workload, "N": N, "P": w["P"], "mode": "direct" if w["direct"] else "pfb",
                    "n_pol": n_pol, "n_int": w["n_int"], "block_samples": w["block"], "blocks": w["blocks"],

@@ -79,12 +79,17 @@ typedef enum { PFBS_MODE_PFB = 0, PFBS_MODE_DIRECT = 1 } pfbs_mode;
  * split into FP16 hi + lo pairs, three products per stage (Wlo*hi + Whi*lo +
  * Whi*hi); accuracy of the FP32 path.  The first radix-2/4/8 stage, the
  * inter-stage and four-step twiddles, the pre-filter, the products and the
- * accumulation stay FP32 in every precision.  Batches (pfbs_batch_create)
+ * accumulation stay FP32 in every precision.  MIXED: the single pass and the
+ * column pass of the two-pass FFT in FP32, the row pass as MFMA_FP16X2; the
+ * row pass is where a strong tone's rounding error concentrates (its energy
+ * sits in one intermediate row), so MIXED meets the FP32 path's accuracy with
+ * the faster 256-point column split at every N.  Batches (pfbs_batch_create)
  * take FP32 plans only. */
 typedef enum {
     PFBS_PREC_FP32 = 0,
     PFBS_PREC_MFMA_FP16 = 1,
-    PFBS_PREC_MFMA_FP16X2 = 2
+    PFBS_PREC_MFMA_FP16X2 = 2,
+    PFBS_PREC_MIXED = 3
 } pfbs_precision;
 
 /* Full plan description.  Fields beyond the six of pfbs_plan_create:

@@ -80,6 +80,7 @@ struct pfbs_plan {
     int64_t N;
     int32_t P;
     int32_t window, mode, npol, precision, device;
+    int prec_front, prec_back;  // kernel arithmetic of the single/column pass and of the row pass
     int64_t n_int;
     int32_t nprod;
     bool pfb;
@@ -187,7 +188,7 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
     if (d->n_pol != 1 && d->n_pol != 2) return fail(PFBS_ERR_INVALID, "n_pol=%d must be 1 or 2", d->n_pol);
     if (d->n_int < 1) return fail(PFBS_ERR_INVALID, "n_int=%lld must be >= 1", (long long)d->n_int);
     if (d->precision != PFBS_PREC_FP32 && d->precision != PFBS_PREC_MFMA_FP16 &&
-        d->precision != PFBS_PREC_MFMA_FP16X2)
+        d->precision != PFBS_PREC_MFMA_FP16X2 && d->precision != PFBS_PREC_MIXED)
         return fail(PFBS_ERR_INVALID, "unknown precision %d", d->precision);
     if (d->chunk < 0 || d->chunk > 65536) return fail(PFBS_ERR_INVALID, "chunk=%d out of range", d->chunk);
     if (d->split_n2 != 0) {
@@ -338,15 +339,19 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->mode = desc->mode;
     p->npol = desc->n_pol;
     p->precision = desc->precision;
+    p->prec_front = desc->precision == PFBS_PREC_MIXED ? PFBS_PREC_FP32 : desc->precision;
+    p->prec_back = desc->precision == PFBS_PREC_MIXED ? PFBS_PREC_MFMA_FP16X2 : desc->precision;
     p->device = dev;
     p->n_int = desc->n_int;
     p->nprod = p->npol == 2 ? 4 : 1;
     p->fourstep = p->N > kMaxSinglePass;
     if (p->fourstep) {
-        // Column length: 256 keeps the int8 rows of a column tile 64 bytes wide;
-        // from 2^18 channels 512 is used, whose shorter rows of the row pass
-        // measured the smaller worst-channel rounding error next to strong tones.
-        p->N2 = desc->split_n2 ? desc->split_n2 : (p->N >= (int64_t(1) << 18) ? 512 : 256);
+        // Column length: 256 keeps the int8 rows of a column tile 64 bytes wide.
+        // From 2^18 channels an FP32 row pass is given the shorter rows of 512
+        // (the smaller worst-channel rounding error next to strong tones); a
+        // matrix-core row pass (MIXED) is accurate enough with 256.
+        const bool long_rows_ok = p->prec_back != PFBS_PREC_FP32;
+        p->N2 = desc->split_n2 ? desc->split_n2 : (p->N >= (int64_t(1) << 18) && !long_rows_ok ? 512 : 256);
         p->N1 = p->N / p->N2;
         p->gA = make_geo((int)p->N2);
         p->gB = make_geo((int)p->N1, back_tile(p->N1));
@@ -645,11 +650,11 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
 pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s) {
     if (w.any) {
         if (!p->fourstep) {
-            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(w.single, p->npol, p->pfb, true, p->precision, w.single_chunks, s); }));
+            PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(w.single, p->npol, p->pfb, true, p->prec_front, w.single_chunks, s); }));
         } else {
             for (const Group &g : w.groups) {
-                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(g.fa, p->npol, p->pfb, false, p->precision, g.na, s); }));
-                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(g.ba, p->npol, p->precision, g.nc, s); }));
+                PFBS_HIP(p, timed(p, 1, s, [&] { return launch_front(g.fa, p->npol, p->pfb, false, p->prec_front, g.na, s); }));
+                PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(g.ba, p->npol, p->prec_back, g.nc, s); }));
             }
         }
         PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(w.ra, w.n_dumps, s); }));

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpfbspec.so")
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOMEM, ERR_DEVICE, ERR_STATE = range(6)
 WINDOW_HANN_SINC, WINDOW_RECT, WINDOW_CUSTOM = 0, 1, 2
 MODE_PFB, MODE_DIRECT = 0, 1
-PREC_FP32, PREC_MFMA_FP16, PREC_MFMA_FP16X2 = 0, 1, 2
+PREC_FP32, PREC_MFMA_FP16, PREC_MFMA_FP16X2, PREC_MIXED = 0, 1, 2, 3
 
 # Every entry point declared in include/pfbspec.h.
 EXPORTS = (

@@ -22,20 +22,20 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 C16 = 64.0
-X2, F16 = pf.PREC_MFMA_FP16X2, pf.PREC_MFMA_FP16
+X2, F16, MIX = pf.PREC_MFMA_FP16X2, pf.PREC_MFMA_FP16, pf.PREC_MIXED
 
 
 @pytest.mark.parametrize("N,n_int", [(4096, 1024), (65536, 1024), (524288, 128)])
 def test_precision_study_first_dump(N, n_int):
     """The c2 stream (sigma=20 noise + correlated tone) at the three lengths
-    of the precision study, 8-tap PFB, first dump: FP32 and FP16X2 within
-    1e-5 of the oracle, FP16 within its roundoff bound."""
+    of the precision study, 8-tap PFB, first dump: FP32, FP16X2 and MIXED
+    within 1e-5 of the oracle, FP16 within its roundoff bound."""
     P = 8
     n = (n_int + P - 1) * N
     x = synth.generate(synth.spec_c2(n_ref=N), 0, n)
     ref = oracle.dumps(x, N, P, oracle.taps(N, P), False, n_int, which=[0])[0]
     errs = {}
-    for prec in (pf.PREC_FP32, X2, F16):
+    for prec in (pf.PREC_FP32, X2, F16, MIX):
         plan = pf.Plan(N, P, n_pol=2, n_int=n_int, precision=prec)
         d, _, _ = run_stream(plan, x, [max(P, (1 << 24) // N)])
         plan.close()
@@ -45,7 +45,24 @@ def test_precision_study_first_dump(N, n_int):
             assert within_fp32_bound(d[0], ref, N, u=U16, c=C16) <= 1.0, errs
         else:
             assert errs[prec] <= TOL, errs
-    print("max relative error N=%d: fp32 %.3g fp16x2 %.3g fp16 %.3g" % (N, errs[0], errs[X2], errs[F16]))
+    print("max relative error N=%d: fp32 %.3g fp16x2 %.3g fp16 %.3g mixed %.3g"
+          % (N, errs[0], errs[X2], errs[F16], errs[MIX]))
+
+
+def test_mixed_config3_first_dump_within_1e5():
+    """N=524288 dual-pol, 8-tap PFB, the three-tone + pulse stream, first dump
+    of 64 spectra: the MIXED precision (FP32 column pass, FP16X2 row pass) at
+    its default 256-point column split stays within 1e-5, where an all-FP32
+    FFT with that split does not (1.2e-5 at the strongest tone's row)."""
+    N, blk = 1 << 19, 1 << 26
+    x = synth.generate(synth.spec_c3(), 0, blk)
+    plan = pf.Plan(N, 8, n_pol=2, n_int=64, precision=MIX)
+    assert plan.info()["split_n2"] == 256
+    dumps, _, cnt = run_stream(plan, x, [blk // N])
+    assert dumps.shape[0] == 1
+    ref = oracle.dumps(x, N, 8, oracle.taps(N, 8), False, 64, which=[0])
+    e = rel_err(dumps[0], ref[0])
+    assert e.max() <= TOL, e.max()
 
 
 CASES = [
@@ -63,7 +80,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [X2, F16])
+@pytest.mark.parametrize("prec", [X2, F16, MIX])
 @pytest.mark.parametrize("N,P,mode,n_pol,n_int,frames,kw", CASES)
 def test_dumps_match_oracle(prec, N, P, mode, n_pol, n_int, frames, kw):
     """Every sub-FFT length and pass layout of both kernels (single pass,
@@ -79,7 +96,7 @@ def test_dumps_match_oracle(prec, N, P, mode, n_pol, n_int, frames, kw):
     S = oracle.num_spectra(T, N, P, direct)
     assert dumps.shape[0] == S // n_int and cnt == S - (S // n_int) * n_int
     ref = oracle.dumps(x, N, P, h, direct, n_int)
-    u, c = (U32, 8.0) if prec == X2 else (U16, C16)
+    u, c = (U16, C16) if prec == F16 else (U32, 8.0)
     for d in range(dumps.shape[0]):
         r = within_fp32_bound(dumps[d], ref[d], N, u=u, c=c)
         assert r <= 1.0, (d, r, rel_err(dumps[d], ref[d]).max())
