@@ -46,6 +46,7 @@ extern "C" {
 
 typedef struct pfbs_plan pfbs_plan;    /* opaque; owns all device state of one stream */
 typedef struct pfbs_batch pfbs_batch;  /* opaque; several plans run by one launch sequence */
+typedef struct pfbs_hstream pfbs_hstream;  /* opaque; a plan fed from host memory */
 
 typedef enum {
     PFBS_OK = 0,
@@ -256,6 +257,46 @@ pfbs_status pfbs_batch_destroy(pfbs_batch *b);
 
 /* The plan of sub-band i of a batch (owned by the batch), or NULL. */
 pfbs_plan *pfbs_batch_plan(pfbs_batch *b, int32_t i);
+
+/* Page-locked host memory (hipHostMalloc) of `bytes` bytes, for blocks and
+ * dumps that travel asynchronously; release with pfbs_host_free (NULL is
+ * accepted there). */
+pfbs_status pfbs_host_alloc(void **out, int64_t bytes);
+pfbs_status pfbs_host_free(void *p);
+
+/* Host-fed streaming (the paper's per-block loop of copy in, compute, copy
+ * out, Section 4 algorithm list, with the copies overlapped by streams as
+ * its Section 5 suggests): a plan plus `depth` (2..16) device slots, each a
+ * block buffer of max_block_samples time samples and a dump buffer, and
+ * three streams (copy in, compute, copy out) chained by events, so that block
+ * i+1 crosses PCIe while block i is computed.  The plan's device state and
+ * rules are those of pfbs_plan_create_ex(desc). */
+pfbs_status pfbs_hstream_create(pfbs_hstream **out, const pfbs_plan_desc *desc, int64_t max_block_samples,
+                                int32_t depth);
+
+/* Queue one block and return at once.
+ *   h_block        : host, int8 [n_time_samples][n_pol][2]; page-locked
+ *                    memory (pfbs_host_alloc) makes the copy asynchronous;
+ *                    must stay unchanged until the push has completed;
+ *   n_time_samples : a positive multiple of N, at most max_block_samples;
+ *   h_dumps        : host, float [dump_capacity][n_prod][N], receives this
+ *                    block's dumps (as pfbs_execute writes them); valid once
+ *                    the push has completed; may be NULL when none complete;
+ *   n_dumps_written: host, set at return.
+ * A push has completed after pfbs_hstream_sync, or once `depth` later pushes
+ * have returned (a push waits on the host for the slot it reuses). */
+pfbs_status pfbs_hstream_push(pfbs_hstream *s, const void *h_block, int64_t n_time_samples, float *h_dumps,
+                              int64_t dump_capacity, int64_t *n_dumps_written);
+
+/* Wait until every queued push has completed. */
+pfbs_status pfbs_hstream_sync(pfbs_hstream *s);
+
+/* Wait for the queued work, then release everything (the plan too).  NULL
+ * is accepted. */
+pfbs_status pfbs_hstream_destroy(pfbs_hstream *s);
+
+/* The plan inside a host stream (owned by it), or NULL. */
+pfbs_plan *pfbs_hstream_plan(pfbs_hstream *s);
 
 #ifdef __cplusplus
 }

@@ -132,6 +132,9 @@ const void *batch_tail_fn();
 
 namespace pfbs {
 
+// Set the calling thread's pfbs_last_error text and return st (plan.cpp).
+pfbs_status record_error(pfbs_status st, const char *msg);
+
 // ---- autotune cache (autotune.cpp) ----
 // Fill *out from the newest cache line matching desc's shape on the current
 // device (speed-only fields); with measure_if_missing, run the autotuner when

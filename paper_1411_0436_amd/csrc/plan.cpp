@@ -38,6 +38,17 @@ pfbs_status fail(pfbs_status st, const char *fmt, ...) {
     return st;
 }
 
+}  // namespace
+
+namespace pfbs {
+pfbs_status record_error(pfbs_status st, const char *msg) {
+    g_err = msg;
+    return st;
+}
+}  // namespace pfbs
+
+namespace {
+
 constexpr uint32_t kMagic = 0x50464253u;  // "PFBS"
 constexpr uint32_t kDead = 0xdeadbeefu;
 

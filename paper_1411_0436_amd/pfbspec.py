@@ -25,7 +25,8 @@ EXPORTS = (
     "pfbs_execute", "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
     "pfbs_plan_get_info", "pfbs_last_error", "pfbs_batch_create", "pfbs_batch_execute",
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
-    "pfbs_autotune",
+    "pfbs_autotune", "pfbs_host_alloc", "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push",
+    "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -100,10 +101,20 @@ def load(path: str = LIB_PATH):
                                 ctypes.POINTER(ctypes.c_double)]
     L.pfbs_batch_plan.argtypes = [vp, i32]
     L.pfbs_batch_plan.restype = vp
+    L.pfbs_host_alloc.argtypes = [ctypes.POINTER(vp), i64]
+    L.pfbs_host_free.argtypes = [vp]
+    L.pfbs_hstream_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), i64, i32]
+    L.pfbs_hstream_push.argtypes = [vp, vp, i64, vp, i64, pi64]
+    L.pfbs_hstream_sync.argtypes = [vp]
+    L.pfbs_hstream_destroy.argtypes = [vp]
+    L.pfbs_hstream_plan.argtypes = [vp]
+    L.pfbs_hstream_plan.restype = vp
     for name in ("pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_execute",
                  "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
                  "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy",
-                 "pfbs_plan_timing", "pfbs_plan_timing_read", "pfbs_autotune"):
+                 "pfbs_plan_timing", "pfbs_plan_timing_read", "pfbs_autotune", "pfbs_host_alloc",
+                 "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push", "pfbs_hstream_sync",
+                 "pfbs_hstream_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -271,6 +282,82 @@ class Batch:
             for p in self.plans:
                 p._h = ctypes.c_void_p()
             _check(self._lib.pfbs_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostBuffer:
+    """Page-locked host memory (pfbs_host_alloc) seen as a numpy array."""
+
+    def __init__(self, shape, dtype):
+        import numpy as np
+        self._lib = load()
+        dt = np.dtype(dtype)
+        n = int(np.prod(shape)) * dt.itemsize
+        self._p = ctypes.c_void_p()
+        _check(self._lib.pfbs_host_alloc(ctypes.byref(self._p), n))
+        raw = (ctypes.c_uint8 * n).from_address(self._p.value)
+        self.array = np.frombuffer(raw, dtype=dt).reshape(shape)
+
+    @property
+    def ptr(self) -> int:
+        return self._p.value
+
+    def close(self):
+        if self._p:
+            self.array = None
+            _check(self._lib.pfbs_host_free(self._p))
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostStream:
+    """A plan fed from host memory (pfbs_hstream): push() queues a block's
+    host-to-device copy, its execution and the copy of its dumps back, on
+    three streams; sync() waits for all of them."""
+
+    def __init__(self, N: int, P: int, max_block_samples: int, depth: int = 3, **kw):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        d = make_desc(N, P, **kw)
+        _check(self._lib.pfbs_hstream_create(ctypes.byref(self._h), ctypes.byref(d), max_block_samples, depth))
+        self.plan = Plan._wrap(self._lib.pfbs_hstream_plan(self._h), self)
+        self.N, self.n_pol, self.n_prod = self.plan.N, self.plan.n_pol, self.plan.n_prod
+
+    def push(self, block, dumps=None) -> int:
+        """block: C-contiguous int8 numpy array [n, n_pol, 2] (page-locked for an
+        asynchronous copy); dumps: float32 numpy array [cap, n_prod, N] or None.
+        Both must be left alone until the push has completed (sync, or `depth`
+        later pushes)."""
+        import numpy as np
+        assert block.dtype == np.int8 and block.flags.c_contiguous
+        n = block.size // (2 * self.n_pol)
+        cap = 0 if dumps is None else dumps.size // (self.n_prod * self.N)
+        if dumps is not None:
+            assert dumps.dtype == np.float32 and dumps.flags.c_contiguous
+        out = ctypes.c_int64(0)
+        _check(self._lib.pfbs_hstream_push(self._h, block.ctypes.data, n,
+                                           None if dumps is None else dumps.ctypes.data, cap,
+                                           ctypes.byref(out)))
+        return out.value
+
+    def sync(self):
+        _check(self._lib.pfbs_hstream_sync(self._h))
+
+    def close(self):
+        if self._h:
+            self.plan._h = ctypes.c_void_p()
+            _check(self._lib.pfbs_hstream_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):
