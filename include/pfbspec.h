@@ -93,6 +93,14 @@ typedef enum {
     PFBS_PREC_MIXED = 3
 } pfbs_precision;
 
+/* Form of the dumps (and of pfbs_flush's partial sum).  PRODUCTS: the four
+ * integrated products |X|^2, |Y|^2, Re XY*, Im XY* (Section 4).  STOKES
+ * (two polarisations only): I = |X|^2 + |Y|^2, Q = |X|^2 - |Y|^2,
+ * U = 2 Re XY*, V = -2 Im XY*, the Stokes parameters of linear feeds, which
+ * the paper notes follow from the four products (Section 4); computed in
+ * FP32 from the integrated products. */
+typedef enum { PFBS_OUT_PRODUCTS = 0, PFBS_OUT_STOKES = 1 } pfbs_output;
+
 /* Full plan description.  Fields beyond the six of pfbs_plan_create:
  *   precision   : see pfbs_precision;
  *   custom_taps : host array of P*N doubles, read during the call only,
@@ -105,6 +113,10 @@ typedef enum {
  *   group_bytes : bound on the intermediate buffer of the two-pass FFT
  *                 (0 = automatic);
  *   col_run     : spectra per workgroup of the column pass (0 = automatic);
+ *   output      : see pfbs_output (batched plans: PRODUCTS only);
+ *   fftshift    : 1 = each dump row in shifted channel order (channel k at
+ *                 position (k + N/2) mod N, negative frequencies first);
+ *                 batched plans: 0 only;
  *   stream_z    : 1 = streaming (non-temporal) stores and loads of the
  *                 two-pass intermediate, 0 = ordinary ones.
  * The last five only change speed, never results beyond FP32 rounding order.
@@ -127,6 +139,8 @@ typedef struct {
     int64_t group_bytes;
     int32_t col_run;
     int32_t stream_z;
+    int32_t output;     /* pfbs_output */
+    int32_t fftshift;   /* 1: channels in shifted order, k' = (k + N/2) mod N */
 } pfbs_plan_desc;
 
 /* Create a plan (FP32 arithmetic; Section 4, initialisation: coefficients are

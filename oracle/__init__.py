@@ -182,3 +182,22 @@ def tail(x: np.ndarray, N: int, P: int, h: Optional[np.ndarray], direct: bool, n
     S = num_spectra(x.shape[0], N, P, direct)
     j0 = (S // n_int) * n_int
     return integrate(x, N, P, h, direct, j0, S, n_threads), S - j0
+
+
+def stokes(prod: np.ndarray) -> np.ndarray:
+    """Integrated products [..., 4, N] (|X|^2, |Y|^2, Re XY*, Im XY*) -> Stokes
+    parameters of linear feeds [..., 4, N] = I, Q, U, V with I = |X|^2 + |Y|^2,
+    Q = |X|^2 - |Y|^2, U = 2 Re XY*, V = -2 Im XY* (the paper notes that the
+    Stokes parameters follow from the four products, Section 4; the sign of V
+    is the reading recorded with the library's output option)."""
+    p = np.asarray(prod, dtype=np.float64)
+    xx, yy, re, im = p[..., 0, :], p[..., 1, :], p[..., 2, :], p[..., 3, :]
+    return np.stack([xx + yy, xx - yy, 2.0 * re, -2.0 * im], axis=-2)
+
+
+def fftshift(rows: np.ndarray) -> np.ndarray:
+    """Channel order of the shifted output: position m holds channel
+    (m + N/2) mod N along the last axis (negative frequencies first)."""
+    r = np.asarray(rows)
+    N = r.shape[-1]
+    return r[..., (np.arange(N) + N // 2) % N]

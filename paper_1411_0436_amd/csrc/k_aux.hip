@@ -1,5 +1,7 @@
 // Auxiliary kernels of the spectrometer: dump reduction, tap-history carry,
 // pre-filter test hook and the FP64 table generators; launch helpers.
+#include <algorithm>
+
 #include "fft_common.h"
 
 namespace pfbs {
@@ -72,8 +74,43 @@ __device__ void reduce_body(const ReduceArgs &a, int bx, int by, int bz) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
-    reduce_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+// grid.y is capped at 65535: a workgroup row walks dumps y, y + gridDim.y, ...
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a, int n_dumps) {
+    for (int by = blockIdx.y; by < n_dumps; by += gridDim.y) {
+        reduce_body(a, blockIdx.x, by, blockIdx.z);
+        __syncthreads();  // the LDS tile is reused by the next dump
+    }
+}
+
+// ---------------------------------------------------------- dump form -----
+
+// Dump row y (blockIdx.y), channel pair (k, k + N/2) per thread, in place:
+// the four products of a channel become I = XX + YY, Q = XX - YY,
+// U = 2 Re XY*, V = -2 Im XY* (stokes), and channel k moves to position
+// (k + N/2) mod N (shift), i.e. the two halves of the row swap.
+__global__ __launch_bounds__(256) void k_dump_format(float *out, long long n_dumps, long long N, int n_prod,
+                                                     int stokes, int shift) {
+    const long long h = N / 2;
+    const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (k >= h) return;
+    for (long long y = blockIdx.y; y < n_dumps; y += gridDim.y) {
+    float *row = out + y * n_prod * N;
+    float a[4], b[4];
+    for (int q = 0; q < n_prod; ++q) {
+        a[q] = row[q * N + k];
+        b[q] = row[q * N + k + h];
+    }
+    if (stokes) {
+        const float ai = a[0] + a[1], aq = a[0] - a[1], au = 2.f * a[2], av = -2.f * a[3];
+        const float bi = b[0] + b[1], bq = b[0] - b[1], bu = 2.f * b[2], bv = -2.f * b[3];
+        a[0] = ai; a[1] = aq; a[2] = au; a[3] = av;
+        b[0] = bi; b[1] = bq; b[2] = bu; b[3] = bv;
+    }
+    for (int q = 0; q < n_prod; ++q) {
+        row[q * N + k] = shift ? b[q] : a[q];
+        row[q * N + k + h] = shift ? a[q] : b[q];
+    }
+    }
 }
 
 // ------------------------------------------------------------ history -----
@@ -271,10 +308,21 @@ hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s) {
+    if (n_dumps <= 0) return hipSuccess;
+    const unsigned gy = (unsigned)std::min(n_dumps, 65535);
     dim3 grid;
-    if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / 8) * (a.N1 / 32)), (unsigned)n_dumps, (unsigned)a.n_prod);
-    else grid = dim3((unsigned)((a.N + 255) / 256), (unsigned)n_dumps, (unsigned)a.n_prod);
-    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a);
+    if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / 8) * (a.N1 / 32)), gy, (unsigned)a.n_prod);
+    else grid = dim3((unsigned)((a.N + 255) / 256), gy, (unsigned)a.n_prod);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a, n_dumps);
+    return hipGetLastError();
+}
+
+hipError_t launch_dump_format(float *out, long long n_dumps, long long N, int n_prod, int stokes, int shift,
+                              hipStream_t s) {
+    if (n_dumps <= 0) return hipSuccess;
+    if ((stokes && n_prod != 4) || N < 2) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)std::min<long long>(n_dumps, 65535));
+    hipLaunchKernelGGL(k_dump_format, grid, dim3(256), 0, s, out, n_dumps, N, n_prod, stokes, shift);
     return hipGetLastError();
 }
 

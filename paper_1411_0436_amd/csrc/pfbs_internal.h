@@ -152,6 +152,10 @@ hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int
                         hipStream_t s);
 hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s);
+// In place on n_dumps rows of [n_prod][N]: products -> Stokes, and/or the
+// shifted channel order.
+hipError_t launch_dump_format(float *out, long long n_dumps, long long N, int n_prod, int stokes, int shift,
+                              hipStream_t s);
 hipError_t launch_history(uint8_t *dst, const Frames &fr, long long F, int H, long long frame_bytes,
                           hipStream_t s);
 hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long long N, int P,

@@ -104,6 +104,7 @@ struct pfbs_plan {
     int64_t C;
     int64_t group_spectra;
     int ga_force;        // column-pass spectra per workgroup (0 = automatic)
+    int out_stokes, out_shift;  // dump form: Stokes parameters, shifted channel order
     int znt;             // streaming stores/loads of the four-step intermediate
     // device state
     float *taps;
@@ -212,6 +213,11 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
     if (d->group_bytes < 0) return fail(PFBS_ERR_INVALID, "group_bytes < 0");
     if (d->col_run < 0 || d->col_run > 64) return fail(PFBS_ERR_INVALID, "col_run=%d out of [0, 64]", d->col_run);
     if (d->stream_z != 0 && d->stream_z != 1) return fail(PFBS_ERR_INVALID, "stream_z must be 0 or 1");
+    if (d->output != PFBS_OUT_PRODUCTS && d->output != PFBS_OUT_STOKES)
+        return fail(PFBS_ERR_INVALID, "unknown output form %d", d->output);
+    if (d->output == PFBS_OUT_STOKES && d->n_pol != 2)
+        return fail(PFBS_ERR_INVALID, "Stokes output needs two polarisations");
+    if (d->fftshift != 0 && d->fftshift != 1) return fail(PFBS_ERR_INVALID, "fftshift must be 0 or 1");
     if (d->tune < 0 || d->tune > 2) return fail(PFBS_ERR_INVALID, "tune must be 0, 1 or 2");
     return PFBS_OK;
 }
@@ -384,6 +390,8 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->frame_bytes = p->N * 2 * p->npol;
     p->ga_force = desc->col_run;
     p->znt = desc->stream_z;
+    p->out_stokes = desc->output == PFBS_OUT_STOKES;
+    p->out_shift = desc->fftshift;
 
     hipStream_t s = nullptr;
     double *d_custom = nullptr;
@@ -669,6 +677,10 @@ pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s) {
             }
         }
         PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(w.ra, w.n_dumps, s); }));
+        if ((p->out_stokes || p->out_shift) && w.nd_out > 0)
+            PFBS_HIP(p, timed(p, 3, s, [&] {
+                return launch_dump_format(w.ra.out, w.nd_out, p->N, p->nprod, p->out_stokes, p->out_shift, s);
+            }));
     }
     if (w.hist) {
         PFBS_HIP(p, timed(p, 4, s, [&] { return launch_history(p->hist[p->hcur ^ 1], w.fr, w.F, p->P - 1, p->frame_bytes, s); }));
@@ -721,6 +733,9 @@ pfbs_status pfbs_flush(pfbs_plan *p, float *d_partial, int64_t *n_spectra, void 
     ra.flush = 1;
     ra.have_carried = cnt > 0;
     PFBS_HIP(p, launch_reduce(ra, 1, (hipStream_t)stream));
+    if (p->out_stokes || p->out_shift)
+        PFBS_HIP(p, launch_dump_format(d_partial, 1, p->N, p->nprod, p->out_stokes, p->out_shift,
+                                       (hipStream_t)stream));
     *n_spectra = cnt;
     return PFBS_OK;
 }

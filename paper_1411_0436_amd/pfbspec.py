@@ -18,6 +18,7 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOMEM, ERR_DEVICE, ERR_STATE = range(6)
 WINDOW_HANN_SINC, WINDOW_RECT, WINDOW_CUSTOM = 0, 1, 2
 MODE_PFB, MODE_DIRECT = 0, 1
 PREC_FP32, PREC_MFMA_FP16, PREC_MFMA_FP16X2, PREC_MIXED = 0, 1, 2, 3
+OUT_PRODUCTS, OUT_STOKES = 0, 1
 
 # Every entry point declared in include/pfbspec.h.
 EXPORTS = (
@@ -46,6 +47,7 @@ class PlanDesc(ctypes.Structure):
         ("custom_taps", ctypes.c_void_p), ("tune", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("split_n2", ctypes.c_int64), ("group_bytes", ctypes.c_int64),
         ("col_run", ctypes.c_int32), ("stream_z", ctypes.c_int32),
+        ("output", ctypes.c_int32), ("fftshift", ctypes.c_int32),
     ]
 
 
@@ -139,14 +141,14 @@ def _stream_ptr(stream) -> Optional[int]:
 def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_PFB, n_pol: int = 2,
               n_int: int = 1, precision: int = PREC_FP32, device: int = -1, custom_taps=None,
               tune: int = 0, chunk: int = 0, split_n2: int = 0, group_bytes: int = 0,
-              col_run: int = 0, stream_z: int = 0):
+              col_run: int = 0, stream_z: int = 0, output: int = 0, fftshift: int = 0):
     """A PlanDesc; ``custom_taps`` (float64 numpy array) is kept alive on the
     returned object until the plan is created."""
     import numpy as np
     d = PlanDesc(N=N, P=P, window=window, mode=mode, n_pol=n_pol, n_int=n_int,
                  precision=precision, device=device, custom_taps=None, tune=tune,
                  chunk=chunk, split_n2=split_n2, group_bytes=group_bytes,
-                 col_run=col_run, stream_z=stream_z)
+                 col_run=col_run, stream_z=stream_z, output=output, fftshift=fftshift)
     keep = None
     if custom_taps is not None:
         keep = np.ascontiguousarray(custom_taps, dtype=np.float64)

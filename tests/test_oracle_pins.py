@@ -309,6 +309,47 @@ def test_products_sign_convention():
     assert np.allclose(p[3], xy.imag)
 
 
+# --------------------------------------------------------------- Stokes -----
+
+@pytest.mark.parametrize("jones,iquv", [
+    ((1.0, 0.0), (1, 1, 0, 0)),                              # linear along X
+    ((0.0, 1.0), (1, -1, 0, 0)),                             # linear along Y
+    ((2 ** -0.5, 2 ** -0.5), (1, 0, 1, 0)),                  # linear at +45 degrees
+    ((2 ** -0.5, -2 ** -0.5), (1, 0, -1, 0)),                # linear at -45 degrees
+    ((2 ** -0.5, 1j * 2 ** -0.5), (1, 0, 0, 1)),             # circular, Y leading X by 90 degrees
+    ((2 ** -0.5, -1j * 2 ** -0.5), (1, 0, 0, -1)),           # circular, Y lagging
+])
+def test_stokes_of_pure_polarisation_states(jones, iquv):
+    """Fully polarised unit-power waves of known polarisation state, through
+    the oracle's products and Stokes: the textbook parameters of linear feeds
+    (with V signed by the phase of Y relative to X)."""
+    X = np.array([[jones[0], 0.3 * jones[0]]])
+    Y = np.array([[jones[1], 0.3 * jones[1]]])
+    S = oracle.stokes(oracle.products(np.concatenate([X, Y])))
+    assert S.shape == (4, 2)
+    assert np.allclose(S[:, 0], iquv, atol=1e-12)
+    assert np.allclose(S[:, 1], 0.09 * np.array(iquv), atol=1e-12)
+
+
+def test_stokes_fully_polarised_identity_and_unpolarised_noise():
+    """I^2 = Q^2 + U^2 + V^2 for any single Jones vector; independent equal-power
+    noise in X and Y integrates to Q, U, V small against I."""
+    rng = np.random.default_rng(3)
+    XY = rng.normal(size=(2, 64)) + 1j * rng.normal(size=(2, 64))
+    S = oracle.stokes(oracle.products(XY))
+    assert np.allclose(S[0] ** 2, S[1] ** 2 + S[2] ** 2 + S[3] ** 2, rtol=1e-12)
+    Xn = rng.normal(size=(2, 4000, 8)) + 1j * rng.normal(size=(2, 4000, 8))
+    acc = sum(oracle.products(Xn[:, t, :]) for t in range(4000))
+    Sn = oracle.stokes(acc)
+    assert np.all(np.abs(Sn[1:]) < 0.1 * Sn[0])
+
+
+@pytest.mark.parametrize("N", [16, 1024])
+def test_shifted_order_equals_library_fftshift(N):
+    rows = np.random.default_rng(N).normal(size=(3, 4, N))
+    assert np.array_equal(oracle.fftshift(rows), np.fft.fftshift(rows, axes=-1))
+
+
 # ---------------------------------------------------------------- dumps -----
 
 @pytest.mark.parametrize("n_pol", [1, 2])
