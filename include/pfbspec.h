@@ -51,7 +51,7 @@ typedef struct pfbs_hstream pfbs_hstream;  /* opaque; a plan fed from host memor
 typedef enum {
     PFBS_OK = 0,
     PFBS_ERR_INVALID = 1,     /* an argument is out of range or inconsistent   */
-    PFBS_ERR_UNSUPPORTED = 2, /* valid request this build cannot serve         */
+    PFBS_ERR_UNSUPPORTED = 2, /* valid request the library does not support   */
     PFBS_ERR_NOMEM = 3,       /* device or host allocation failed              */
     PFBS_ERR_DEVICE = 4,      /* the HIP runtime reported an error             */
     PFBS_ERR_STATE = 5        /* plan destroyed, poisoned, or used wrongly     */

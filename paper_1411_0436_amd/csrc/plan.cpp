@@ -864,6 +864,8 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
         if (descs[i].n_pol != descs[0].n_pol) return fail(PFBS_ERR_INVALID, "all sub-bands need the same n_pol");
         if (descs[i].precision != PFBS_PREC_FP32)
             return fail(PFBS_ERR_UNSUPPORTED, "sub-band %d: batched launches run the FP32 path", i);
+        if (descs[i].output != PFBS_OUT_PRODUCTS || descs[i].fftshift != 0)
+            return fail(PFBS_ERR_UNSUPPORTED, "sub-band %d: batched launches write the products in natural order", i);
     }
     pfbs_batch *b = new (std::nothrow) pfbs_batch();
     if (!b) return fail(PFBS_ERR_NOMEM, "host allocation");
