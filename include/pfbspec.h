@@ -241,7 +241,9 @@ pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches
  * *best_samples_per_s (may be NULL).  At most max_candidates settings are
  * timed (0 = all).  If the environment variable PFBS_TUNE_CACHE names a file,
  * the result is appended to it as one text line
- *   pfbs-tune-v1 <arch> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z samples_per_s
+ *   pfbs-tune-v2 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z samples_per_s
+ * (version: the source digest of pfbs_version, so a rebuilt library with
+ * changed kernels does not reuse old measurements)
  * and later plans created with tune != 0 reuse the newest matching line.
  * Synchronous; allocates device memory for the block and the trial plans.  */
 pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_samples, int32_t max_candidates,
@@ -249,6 +251,9 @@ pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_samples, int
 
 /* Human-readable detail of the calling thread's last failure ("" if none). */
 const char *pfbs_last_error(void);
+
+/* Library version: "pfbspec <digest of the sources it was built from>". */
+const char *pfbs_version(void);
 
 /* Batched form: several independent sub-band streams (each with its own N, P,
  * mode, n_int and state) processed by one fixed launch sequence per block,

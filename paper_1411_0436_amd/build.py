@@ -37,16 +37,30 @@ def _objdir() -> str:
     return d
 
 
+def source_digest() -> str:
+    """Digest of every library source and the public header: the library
+    version that autotune cache entries are keyed on."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in sorted(os.listdir(CSRC)) + ["../../include/pfbspec.h"]:
+        path = os.path.normpath(os.path.join(CSRC, name))
+        if os.path.isfile(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source (always) and link libpfbspec.so.  Returns its path."""
     od = _objdir()
     objs = []
     procs = []
+    version = ['-DPFBS_SOURCE_DIGEST="%s"' % source_digest()]
     for src in SOURCES:
         obj = os.path.join(od, src + ".o")
         objs.append(obj)
         lang = ["-x", "hip"]
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + version + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

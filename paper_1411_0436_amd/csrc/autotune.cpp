@@ -32,25 +32,31 @@ std::string device_arch() {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
+#ifndef PFBS_SOURCE_DIGEST
+#define PFBS_SOURCE_DIGEST "unknown"
+#endif
+
 struct Line {
-    std::string arch;
+    std::string arch, version;
     long long N, n_int, block, split;
     int P, mode, npol, prec, chunk, col_run, stream_z;
     double sps;
 };
 
 bool parse(const char *s, Line &l) {
-    char tag[32], arch[64];
-    int n = sscanf(s, "%31s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %lf", tag, arch, &l.N, &l.P,
+    char tag[32], arch[64], ver[64];
+    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %lf", tag, arch, ver, &l.N, &l.P,
                    &l.mode, &l.npol, &l.n_int, &l.prec, &l.block, &l.split, &l.chunk, &l.col_run,
                    &l.stream_z, &l.sps);
-    if (n != 14 || strcmp(tag, "pfbs-tune-v1") != 0) return false;
+    if (n != 15 || strcmp(tag, "pfbs-tune-v2") != 0) return false;
     l.arch = arch;
+    l.version = ver;
     return true;
 }
 
 bool same_shape(const Line &l, const std::string &arch, const pfbs_plan_desc *d) {
-    return l.arch == arch && l.N == d->N && l.P == d->P && l.mode == d->mode && l.npol == d->n_pol &&
+    return l.arch == arch && l.version == PFBS_SOURCE_DIGEST && l.N == d->N && l.P == d->P && l.mode == d->mode &&
+           l.npol == d->n_pol &&
            l.n_int == d->n_int && l.prec == d->precision;
 }
 
@@ -80,8 +86,8 @@ void cache_append(const pfbs_plan_desc *d, int64_t block, const pfbs_plan_desc *
     std::lock_guard<std::mutex> lk(g_cache_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "pfbs-tune-v1 %s %lld %d %d %d %lld %d %lld %lld %d %d %d %.6e\n", device_arch().c_str(),
-            (long long)d->N, d->P, d->mode, d->n_pol, (long long)d->n_int, d->precision, (long long)block,
+    fprintf(f, "pfbs-tune-v2 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %.6e\n", device_arch().c_str(),
+            PFBS_SOURCE_DIGEST, (long long)d->N, d->P, d->mode, d->n_pol, (long long)d->n_int, d->precision, (long long)block,
             (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, sps);
     fclose(f);
 }

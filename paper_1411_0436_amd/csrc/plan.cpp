@@ -314,6 +314,11 @@ extern "C" {
 
 const char *pfbs_last_error(void) { return g_err.c_str(); }
 
+#ifndef PFBS_SOURCE_DIGEST
+#define PFBS_SOURCE_DIGEST "unknown"
+#endif
+const char *pfbs_version(void) { return "pfbspec " PFBS_SOURCE_DIGEST; }
+
 pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) {
     if (!out) return fail(PFBS_ERR_INVALID, "out is NULL");
     *out = nullptr;

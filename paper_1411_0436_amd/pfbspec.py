@@ -27,7 +27,7 @@ EXPORTS = (
     "pfbs_plan_get_info", "pfbs_last_error", "pfbs_batch_create", "pfbs_batch_execute",
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
     "pfbs_autotune", "pfbs_host_alloc", "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push",
-    "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan",
+    "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan", "pfbs_version",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     L.pfbs_debug_taps.argtypes = [vp, vp, vp]
     L.pfbs_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.pfbs_last_error.restype = ctypes.c_char_p
+    L.pfbs_version.restype = ctypes.c_char_p
     L.pfbs_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), i32]
     L.pfbs_batch_execute.argtypes = [vp, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64, pi64, i32, vp]
     L.pfbs_batch_destroy.argtypes = [vp]
@@ -120,6 +121,10 @@ def load(path: str = LIB_PATH):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def version() -> str:
+    return load().pfbs_version().decode()
 
 
 def last_error() -> str:

@@ -24,7 +24,10 @@ def test_autotune_returns_valid_setting_and_caches_it(tmp_path, monkeypatch):
     assert fields["split_n2"] in (64, 128, 256, 512)
     assert fields["chunk"] in (8, 16, 32, 64)
     lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("pfbs-tune-v1 gfx950 8192 8 0 2 16 0 ")
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert f[0] == "pfbs-tune-v2" and f[1] == "gfx950" and "pfbspec " + f[2] == pf.version()
+    assert f[3:9] == ["8192", "8", "0", "2", "16", "0"]
     plan = pf.Plan(N, 8, n_pol=2, n_int=16, tune=1)
     info = plan.info()
     assert info["split_n2"] == fields["split_n2"] and info["chunk"] == fields["chunk"]
