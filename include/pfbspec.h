@@ -222,20 +222,25 @@ typedef struct {
 pfbs_status pfbs_plan_get_info(const pfbs_plan *plan, pfbs_plan_info *info);
 
 /* Kernel timing.  With enable != 0 every kernel launch that pfbs_execute makes
- * for this plan is bracketed by a pair of HIP events recorded on the execute
- * stream.  pfbs_plan_timing_read waits for those events, adds their elapsed
- * times (ms) and launch counts per kernel kind into ms[kind] / launches[kind]
- * for kind < n (kinds: 0 single-pass, 1 column pass, 2 row pass, 3 dump
- * reduction, 4 tap history; PFBS_KERNEL_KINDS in all), and forgets them.
- * Intended for measurement; it adds two event records per launch. */
+ * for this plan records its start and stop timestamps into a pair of HIP
+ * events through the dispatch itself (hipExtLaunchKernel), so timing adds no
+ * packets to the stream.  pfbs_plan_timing_read waits for those events, adds
+ * their elapsed times (ms) and launch counts per kernel kind into ms[kind] /
+ * launches[kind] for kind < n (kinds: 0 single-pass, 1 column pass, 2 row
+ * pass, 3 dump reduction and output form, 4 tap history; PFBS_KERNEL_KINDS in
+ * all), and forgets them. */
 #define PFBS_KERNEL_KINDS 5
 pfbs_status pfbs_plan_timing(pfbs_plan *plan, int32_t enable);
+/* The same for a subset of kinds: bit k of `kinds` times kind k (0 = off). */
+pfbs_status pfbs_plan_timing_kinds(pfbs_plan *plan, uint32_t kinds);
 pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches, int32_t n);
 
 /* Autotuner.  Times candidate settings of the speed-only fields (split_n2,
  * chunk, col_run, stream_z) for the plan shape in *desc on its device, each
- * on the same synthetic device block of block_samples time samples (a
- * positive multiple of N; 0 = 2^24), with HIP events around a few blocks, and
+ * on the same synthetic stream of device blocks of block_samples time samples
+ * (a positive multiple of N; 0 = 2^24; as many distinct blocks as make at
+ * least 512 MB, at most 16, so the input streams from HBM and not from the
+ * caches), with HIP events around two passes over them, and
  * writes the fastest into *best (a copy of *desc with those fields set and
  * tune = 0) and its throughput in complex samples per second into
  * *best_samples_per_s (may be NULL).  At most max_candidates settings are
@@ -245,7 +250,7 @@ pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches
  * (version: the source digest of pfbs_version, so a rebuilt library with
  * changed kernels does not reuse old measurements)
  * and later plans created with tune != 0 reuse the newest matching line.
- * Synchronous; allocates device memory for the block and the trial plans.  */
+ * Synchronous; allocates device memory for the blocks and the trial plans. */
 pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_samples, int32_t max_candidates,
                           pfbs_plan_desc *best, double *best_samples_per_s);
 

@@ -6,6 +6,7 @@
 // kept, optionally in a plain-text cache file (PFBS_TUNE_CACHE).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -108,9 +109,10 @@ std::vector<int64_t> splits_for(int64_t N) {
     return v;
 }
 
-// Time one candidate: average seconds per block over `reps` blocks after
-// `warm` untimed ones.  Returns < 0 when the candidate cannot be created.
-double time_candidate(const pfbs_plan_desc *c, const void *d_block, int64_t n, float *d_dumps,
+// Time one candidate: average seconds per block over `reps` passes over the
+// nb blocks (consecutive blocks of one stream) after `warm` untimed passes.
+// Returns < 0 when the candidate cannot be created.
+double time_candidate(const pfbs_plan_desc *c, const uint8_t *d_blocks, int nb, int64_t n, float *d_dumps,
                       int64_t cap, hipStream_t s, int warm, int reps) {
     pfbs_plan *p = nullptr;
     if (pfbs_plan_create_ex(&p, c) != PFBS_OK) return -1.0;
@@ -119,14 +121,15 @@ double time_candidate(const pfbs_plan_desc *c, const void *d_block, int64_t n, f
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
         int64_t nd = 0;
         bool ok = true;
-        for (int i = 0; i < warm && ok; ++i)
-            ok = pfbs_execute(p, d_block, n, d_dumps, cap, &nd, s) == PFBS_OK;
+        const size_t bytes = (size_t)n * 2 * c->n_pol;
+        for (int i = 0; i < warm * nb && ok; ++i)
+            ok = pfbs_execute(p, d_blocks + (size_t)(i % nb) * bytes, n, d_dumps, cap, &nd, s) == PFBS_OK;
         ok = ok && hipEventRecord(e0, s) == hipSuccess;
-        for (int i = 0; i < reps && ok; ++i)
-            ok = pfbs_execute(p, d_block, n, d_dumps, cap, &nd, s) == PFBS_OK;
+        for (int i = 0; i < reps * nb && ok; ++i)
+            ok = pfbs_execute(p, d_blocks + (size_t)(i % nb) * bytes, n, d_dumps, cap, &nd, s) == PFBS_OK;
         ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.f;
-        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t = ms * 1e-3 / reps;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t = ms * 1e-3 / (reps * nb);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
@@ -196,24 +199,27 @@ extern "C" pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_s
     if (max_candidates > 0 && (int)cands.size() > max_candidates) cands.resize(max_candidates);
 
     const size_t bytes = (size_t)n * 2 * base.n_pol;
+    // enough distinct blocks (at least 512 MB, at most 16) that the input
+    // streams from HBM as in a real run instead of staying in the caches
+    const int nb = (int)std::min<size_t>(16, std::max<size_t>(1, ((size_t)512 << 20) / bytes));
     void *d_block = nullptr;
     float *d_dumps = nullptr;
     const int64_t nprod = base.n_pol == 2 ? 4 : 1;
     const int64_t cap = n / base.N + 1;  // at most one dump per spectrum
     hipStream_t s = nullptr;
     pfbs_status rs = PFBS_OK;
-    if (hipMalloc(&d_block, bytes) != hipSuccess ||
+    if (hipMalloc(&d_block, bytes * nb) != hipSuccess ||
         hipMalloc((void **)&d_dumps, (size_t)cap * nprod * base.N * sizeof(float)) != hipSuccess ||
         hipStreamCreate(&s) != hipSuccess) {
         rs = PFBS_ERR_NOMEM;
     }
     double best_t = -1.0;
     pfbs_plan_desc winner = base;
-    if (rs == PFBS_OK && pfbs::launch_synth((uint32_t *)d_block, (long long)(bytes / 4), 0x5eedu, s) != hipSuccess)
+    if (rs == PFBS_OK && pfbs::launch_synth((uint32_t *)d_block, (long long)(bytes * nb / 4), 0x5eedu, s) != hipSuccess)
         rs = PFBS_ERR_DEVICE;
     if (rs == PFBS_OK) {
         for (const pfbs_plan_desc &c : cands) {
-            const double t = time_candidate(&c, d_block, n, d_dumps, cap, s, 2, 4);
+            const double t = time_candidate(&c, (const uint8_t *)d_block, nb, n, d_dumps, cap, s, 1, 2);
             if (t > 0 && (best_t < 0 || t < best_t)) {
                 best_t = t;
                 winner = c;

@@ -313,7 +313,7 @@ hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s) {
     dim3 grid;
     if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / 8) * (a.N1 / 32)), gy, (unsigned)a.n_prod);
     else grid = dim3((unsigned)((a.N + 255) / 256), gy, (unsigned)a.n_prod);
-    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a, n_dumps);
+    PFBS_LAUNCH(k_reduce, grid, dim3(256), 0, s, a, n_dumps);
     return hipGetLastError();
 }
 
@@ -322,14 +322,14 @@ hipError_t launch_dump_format(float *out, long long n_dumps, long long N, int n_
     if (n_dumps <= 0) return hipSuccess;
     if ((stokes && n_prod != 4) || N < 2) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)std::min<long long>(n_dumps, 65535));
-    hipLaunchKernelGGL(k_dump_format, grid, dim3(256), 0, s, out, n_dumps, N, n_prod, stokes, shift);
+    PFBS_LAUNCH(k_dump_format, grid, dim3(256), 0, s, out, n_dumps, N, n_prod, stokes, shift);
     return hipGetLastError();
 }
 
 hipError_t launch_history(uint8_t *dst, const Frames &fr, long long F, int H, long long frame_bytes,
                           hipStream_t s) {
     const long long vec = frame_bytes / 16;
-    hipLaunchKernelGGL(k_history, dim3(grid_for(H * vec, 256)), dim3(256), 0, s,
+    PFBS_LAUNCH(k_history, dim3(grid_for(H * vec, 256)), dim3(256), 0, s,
                        reinterpret_cast<uint4 *>(dst), fr, F, H, vec);
     return hipGetLastError();
 }

@@ -36,11 +36,11 @@ hipError_t launch_cols_p(const FrontArgs &a, int npol, bool pfb, dim3 grid, dim3
 #define PFBS_CASE(LL)                                                                               \
     case LL:                                                                                        \
         if (npol == 2) {                                                                            \
-            if (pfb) hipLaunchKernelGGL((k_front_cols<2, true, LL, PREC>), grid, block, lds, s, a); \
-            else hipLaunchKernelGGL((k_front_cols<2, false, LL, PREC>), grid, block, lds, s, a);    \
+            if (pfb) PFBS_LAUNCH((k_front_cols<2, true, LL, PREC>), grid, block, lds, s, a); \
+            else PFBS_LAUNCH((k_front_cols<2, false, LL, PREC>), grid, block, lds, s, a);    \
         } else {                                                                                    \
-            if (pfb) hipLaunchKernelGGL((k_front_cols<1, true, LL, PREC>), grid, block, lds, s, a); \
-            else hipLaunchKernelGGL((k_front_cols<1, false, LL, PREC>), grid, block, lds, s, a);    \
+            if (pfb) PFBS_LAUNCH((k_front_cols<1, true, LL, PREC>), grid, block, lds, s, a); \
+            else PFBS_LAUNCH((k_front_cols<1, false, LL, PREC>), grid, block, lds, s, a);    \
         }                                                                                           \
         break;
         PFBS_COLS_CASES(PFBS_CASE)
@@ -56,8 +56,8 @@ hipError_t launch_back_p(const BackArgs &a, int npol, dim3 grid, dim3 block, siz
     switch (a.g.L) {
 #define PFBS_CASE(LL)                                                                     \
     case LL:                                                                              \
-        if (npol == 2) hipLaunchKernelGGL((k_back<2, LL, PREC>), grid, block, lds, s, a); \
-        else hipLaunchKernelGGL((k_back<1, LL, PREC>), grid, block, lds, s, a);           \
+        if (npol == 2) PFBS_LAUNCH((k_back<2, LL, PREC>), grid, block, lds, s, a); \
+        else PFBS_LAUNCH((k_back<1, LL, PREC>), grid, block, lds, s, a);           \
         break;
         PFBS_BACK_CASES(PFBS_CASE)
 #undef PFBS_CASE

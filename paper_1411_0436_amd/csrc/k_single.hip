@@ -19,11 +19,11 @@ hipError_t launch_single_p(const FrontArgs &a, int npol, bool pfb, dim3 grid, di
 #define PFBS_CASE(LL)                                                                                 \
     case LL:                                                                                          \
         if (npol == 2) {                                                                              \
-            if (pfb) hipLaunchKernelGGL((k_front_single<2, true, LL, PREC>), grid, block, lds, s, a); \
-            else hipLaunchKernelGGL((k_front_single<2, false, LL, PREC>), grid, block, lds, s, a);    \
+            if (pfb) PFBS_LAUNCH((k_front_single<2, true, LL, PREC>), grid, block, lds, s, a); \
+            else PFBS_LAUNCH((k_front_single<2, false, LL, PREC>), grid, block, lds, s, a);    \
         } else {                                                                                      \
-            if (pfb) hipLaunchKernelGGL((k_front_single<1, true, LL, PREC>), grid, block, lds, s, a); \
-            else hipLaunchKernelGGL((k_front_single<1, false, LL, PREC>), grid, block, lds, s, a);    \
+            if (pfb) PFBS_LAUNCH((k_front_single<1, true, LL, PREC>), grid, block, lds, s, a); \
+            else PFBS_LAUNCH((k_front_single<1, false, LL, PREC>), grid, block, lds, s, a);    \
         }                                                                                             \
         break;
         PFBS_SINGLE_CASES(PFBS_CASE)

@@ -2,6 +2,7 @@
 // Not part of the public ABI (include/pfbspec.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -131,6 +132,23 @@ const void *batch_tail_fn();
 #include "../../include/pfbspec.h"
 
 namespace pfbs {
+
+// Kernel timing without extra stream packets: while `start` is set, the next
+// library launch on this thread records its start and stop timestamps into
+// the two events through the dispatch itself (hipExtLaunchKernel).
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+#define PFBS_LAUNCH(kernel, grid, block, lds, stream, ...)                                             \
+    do {                                                                                               \
+        if (::pfbs::g_launch_events.start)                                                             \
+            hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, ::pfbs::g_launch_events.start,     \
+                                  ::pfbs::g_launch_events.stop, 0, __VA_ARGS__);                       \
+        else                                                                                           \
+            hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                         \
+    } while (0)
 
 // Set the calling thread's pfbs_last_error text and return st (plan.cpp).
 pfbs_status record_error(pfbs_status st, const char *msg);

@@ -41,6 +41,8 @@ pfbs_status fail(pfbs_status st, const char *fmt, ...) {
 }  // namespace
 
 namespace pfbs {
+thread_local LaunchEvents g_launch_events = {nullptr, nullptr};
+
 pfbs_status record_error(pfbs_status st, const char *msg) {
     g_err = msg;
     return st;
@@ -123,7 +125,7 @@ struct pfbs_plan {
     int64_t frames_seen, spectra_done, dumps_done;
     bool poisoned;
     // optional kernel timing: (kind, start, stop) per launch since the last read
-    bool timing;
+    uint32_t timing;     // bit k: time the launches of kernel kind k
     std::vector<hipEvent_t> ev_pool;
     struct Rec { int kind; int i0; };
     std::vector<Rec> recs;
@@ -265,7 +267,7 @@ void free_plan_memory(pfbs_plan *p) {
 // Run one launch, bracketed by timing events when the plan measures kernels.
 template <typename F>
 hipError_t timed(pfbs_plan *p, int kind, hipStream_t s, F &&launch) {
-    if (!p->timing) return launch();
+    if (!((p->timing >> kind) & 1u)) return launch();
     while (p->ev_pool.size() < p->ev_used + 2) {
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
@@ -273,11 +275,11 @@ hipError_t timed(pfbs_plan *p, int kind, hipStream_t s, F &&launch) {
         p->ev_pool.push_back(e);
     }
     const int i0 = (int)p->ev_used;
-    hipError_t r = hipEventRecord(p->ev_pool[i0], s);
-    if (r != hipSuccess) return r;
-    r = launch();
-    if (r != hipSuccess) return r;
-    r = hipEventRecord(p->ev_pool[i0 + 1], s);
+    // the launch records its own start/stop timestamps (no extra packets)
+    g_launch_events = {p->ev_pool[i0], p->ev_pool[i0 + 1]};
+    hipError_t r = launch();
+    g_launch_events = {nullptr, nullptr};
+    (void)s;
     if (r != hipSuccess) return r;
     p->ev_used += 2;
     p->recs.push_back({kind, i0});
@@ -782,8 +784,13 @@ pfbs_status pfbs_debug_pfb(pfbs_plan *p, const void *d_block, int64_t n, float *
 }
 
 pfbs_status pfbs_plan_timing(pfbs_plan *p, int32_t enable) {
+    return pfbs_plan_timing_kinds(p, enable ? (1u << PFBS_KERNEL_KINDS) - 1u : 0u);
+}
+
+pfbs_status pfbs_plan_timing_kinds(pfbs_plan *p, uint32_t kinds) {
     if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
-    p->timing = enable != 0;
+    if (kinds >> PFBS_KERNEL_KINDS) return fail(PFBS_ERR_INVALID, "unknown kernel kind in mask 0x%x", kinds);
+    p->timing = kinds;
     return PFBS_OK;
 }
 

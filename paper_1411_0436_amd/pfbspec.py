@@ -27,7 +27,7 @@ EXPORTS = (
     "pfbs_plan_get_info", "pfbs_last_error", "pfbs_batch_create", "pfbs_batch_execute",
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
     "pfbs_autotune", "pfbs_host_alloc", "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push",
-    "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan", "pfbs_version",
+    "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan", "pfbs_version", "pfbs_plan_timing_kinds",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH):
     L.pfbs_batch_execute.argtypes = [vp, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64, pi64, i32, vp]
     L.pfbs_batch_destroy.argtypes = [vp]
     L.pfbs_plan_timing.argtypes = [vp, i32]
+    L.pfbs_plan_timing_kinds.argtypes = [vp, ctypes.c_uint32]
+    L.pfbs_plan_timing_kinds.restype = ctypes.c_int
     L.pfbs_plan_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), pi64, i32]
     L.pfbs_autotune.argtypes = [ctypes.POINTER(PlanDesc), i64, i32, ctypes.POINTER(PlanDesc),
                                 ctypes.POINTER(ctypes.c_double)]
@@ -243,8 +245,15 @@ class Plan:
     def debug_taps(self, out, stream=None):
         _check(self._lib.pfbs_debug_taps(self._h, out.data_ptr(), _stream_ptr(stream)))
 
-    def timing(self, enable: bool = True):
-        _check(self._lib.pfbs_plan_timing(self._h, int(enable)))
+    def timing(self, enable: bool = True, kinds=None):
+        """Time every launch (enable), or only the named kernel kinds."""
+        if kinds is None:
+            _check(self._lib.pfbs_plan_timing(self._h, int(enable)))
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << KERNEL_KINDS.index(k)
+            _check(self._lib.pfbs_plan_timing_kinds(self._h, mask if enable else 0))
 
     def timing_read(self) -> dict:
         """{kind: (total ms, launches)} since the last read (waits for the events)."""
