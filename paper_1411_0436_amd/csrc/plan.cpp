@@ -370,12 +370,15 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->nprod = p->npol == 2 ? 4 : 1;
     p->fourstep = p->N > kMaxSinglePass;
     if (p->fourstep) {
-        // Column length: 256 keeps the int8 rows of a column tile 64 bytes wide.
-        // From 2^18 channels an FP32 row pass is given the shorter rows of 512
-        // (the smaller worst-channel rounding error next to strong tones); a
-        // matrix-core row pass (MIXED) is accurate enough with 256.
+        // Column length (measured fastest): 128 up to 2^15 channels (whole
+        // 128-byte int8 rows per column tile), 256 above.  From 2^18 channels
+        // an FP32 row pass is given the shorter rows of 512 (the smaller
+        // worst-channel rounding error next to strong tones); a matrix-core
+        // row pass (MIXED) is accurate enough with 256.
         const bool long_rows_ok = p->prec_back != PFBS_PREC_FP32;
-        p->N2 = desc->split_n2 ? desc->split_n2 : (p->N >= (int64_t(1) << 18) && !long_rows_ok ? 512 : 256);
+        int64_t n2 = p->N <= (int64_t(1) << 15) ? 128 : 256;
+        if (p->N >= (int64_t(1) << 18) && !long_rows_ok) n2 = 512;
+        p->N2 = desc->split_n2 ? desc->split_n2 : n2;
         p->N1 = p->N / p->N2;
         p->gA = make_geo((int)p->N2);
         p->gB = make_geo((int)p->N1, back_tile(p->N1));

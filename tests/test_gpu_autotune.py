@@ -43,7 +43,7 @@ def test_tune_without_cache_entry_keeps_defaults(tmp_path, monkeypatch):
     require_gpu()
     monkeypatch.setenv("PFBS_TUNE_CACHE", str(tmp_path / "empty.txt"))
     plan = pf.Plan(32768, 8, n_pol=2, n_int=4, tune=1)
-    assert plan.info()["split_n2"] == 256
+    assert plan.info()["split_n2"] == 128  # the built-in choice for 2^15 channels
 
 
 def test_single_pass_shape_tunes_chunk_only(tmp_path, monkeypatch):
