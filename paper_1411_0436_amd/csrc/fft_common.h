@@ -322,8 +322,15 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
         mx = fmaxf(fmaxf(mx, fabsf(x[g][1].y)), fabsf(x[g][2].x));
         mx = fmaxf(fmaxf(mx, fabsf(x[g][2].y)), fabsf(x[g][3].x));
         mx = fmaxf(mx, fabsf(x[g][3].y));
-        mx = fmaxf(mx, __shfl_xor(mx, 16));
-        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        // lanes l, l^16, l^32, l^48: the swaps exchange between rows of 16
+        // lanes in registers (each lane ends with its partner's value in one
+        // of the two results and its own in the other)
+        {
+            auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(mx), __float_as_uint(mx), false, false);
+            mx = fmaxf(mx, fmaxf(__uint_as_float(r16[0]), __uint_as_float(r16[1])));
+            auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(mx), __float_as_uint(mx), false, false);
+            mx = fmaxf(mx, fmaxf(__uint_as_float(r32[0]), __uint_as_float(r32[1])));
+        }
         const int sc = 15 - __builtin_amdgcn_frexp_expf(mx);
         half8 bh, bl;
 #pragma unroll
