@@ -210,22 +210,42 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
         for (int s = 0; s < PTS; ++s)
 #pragma unroll
             for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
-        for (int p = 0; p < P; ++p) {
-            // uniform bases, 32-bit unsigned per-lane offsets
+        // uniform bases, 32-bit unsigned per-lane offsets
+        auto tap_loads = [&](int p, W4 (&w4)[PTS / 4], float4 (&h4)[PTS / 4]) {
             const W *fb = frame_ptr<NPOL>(a.fr, j + p, N) + n1_0;
             const float *hb = a.taps + (long long)p * N + n1_0;
 #pragma unroll
             for (int g = 0; g < PTS / 4; ++g) {
                 const int q = tid + NB * g;
                 const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
-                const W4 w4 = *reinterpret_cast<const W4 *>(fb + n);
-                if (PFB) {
-                    const float4 h4 = *reinterpret_cast<const float4 *>(hb + n);
+                w4[g] = *reinterpret_cast<const W4 *>(fb + n);
+                if (PFB) h4[g] = *reinterpret_cast<const float4 *>(hb + n);
+            }
+        };
+        W4 w4[PTS / 4];
+        float4 h4[PTS / 4];
+        tap_loads(0, w4, h4);
+        if constexpr (!PFB) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) tap_fma<NPOL>(y[4 * g + e], part4(h4, e), Sample<NPOL>::part(w4, e));
-                } else {
+            for (int g = 0; g < PTS / 4; ++g)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4, e), y[4 * g + e]);
+                for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4[g], e), y[4 * g + e]);
+        } else {
+            for (int p = 0; p < P; ++p) {
+                // the next tap's loads go out before this tap's arithmetic, so
+                // one tap's memory latency overlaps the previous tap's FMAs
+                // (the last tap reloads itself, from cache, to keep the loop
+                // branch-free)
+                W4 w4n[PTS / 4];
+                float4 h4n[PTS / 4];
+                tap_loads(min(p + 1, P - 1), w4n, h4n);
+#pragma unroll
+                for (int g = 0; g < PTS / 4; ++g) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        tap_fma<NPOL>(y[4 * g + e], part4(h4[g], e), Sample<NPOL>::part(w4[g], e));
+                    w4[g] = w4n[g];
+                    h4[g] = h4n[g];
                 }
             }
         }
