@@ -16,7 +16,7 @@ namespace pfbs {
 // column order and written as the chunk's partial sum.
 template <int NPOL, bool PFB, int L, int PREC = 0>
 __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
-    typedef Geom<L> G;
+    typedef Geom<L, kTilePoints, 5> G;
     typedef typename Sample<NPOL>::word4 W4;
     constexpr int NB = G::TPP * NPOL;      // threads
     constexpr int PTS = kTilePoints / NB;  // pre-filter points per thread (all pols each)
@@ -154,18 +154,31 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
 // dealt to the 8 XCDs round-robin; give each XCD a contiguous range of tiles
 // and walk each tile's spectra consecutively, so the workgroups that share an
 // L2 share taps and frames.  Tiles whose int8 row segments are narrower than
-// a 128-byte line run as a group of TG adjacent tiles that together fill the
-// line, spectrum by spectrum.
+// a 128-byte line run as a group of TGW adjacent tiles that together fill the
+// line, spectrum by spectrum.  With fewer than 8 such groups, each group's
+// spectra are split between 8/groups XCDs instead (a line never straddles two
+// L2s; only the P-1 frames at a split are fetched twice).  Needs the item
+// count to be a multiple of 8, which the plan pads (padded items are empty).
 template <int T, int NPOL>
 __device__ __forceinline__ void cols_tile_item(int ntiles, int bid, int nblk, int &tile, int &item) {
     const int nitems = nblk / ntiles;
-    if ((ntiles & 7) == 0) {
-        constexpr int SEG = T * 2 * NPOL;  // bytes of a tile's row segment
-        constexpr int TGW = SEG >= 128 ? 1 : 128 / SEG;
+    constexpr int SEG = T * 2 * NPOL;  // bytes of a tile's row segment
+    constexpr int TGW = SEG >= 128 ? 1 : 128 / SEG;
+    const int xcd = bid & 7, local = bid >> 3;
+    const int ngroups = ntiles / TGW;
+    if ((ntiles & 7) == 0 && (ntiles >> 3) % TGW == 0) {
+        const int tpx = ntiles >> 3;
+        const int grp = local / (TGW * nitems), rem = local - grp * (TGW * nitems);
+        tile = xcd * tpx + grp * TGW + rem % TGW;
+        item = rem / TGW;
+    } else if (ngroups > 0 && ntiles % TGW == 0 && 8 % ngroups == 0 && nitems % (8 / ngroups) == 0) {
+        const int per = nitems / (8 / ngroups);
+        tile = (xcd % ngroups) * TGW + local % TGW;
+        item = (xcd / ngroups) * per + local / TGW;
+    } else if ((ntiles & 7) == 0) {
         const int tpx = ntiles >> 3;
         int TG = TGW;
         while (tpx % TG) TG >>= 1;
-        const int xcd = bid & 7, local = bid >> 3;
         const int grp = local / (TG * nitems), rem = local - grp * (TG * nitems);
         tile = xcd * tpx + grp * TG + rem % TG;
         item = rem / TG;
@@ -298,10 +311,13 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 // Row-pass tile: at least 1024 points per polarisation (64 threads each), so
 // short rows still give many small workgroups.
 template <int L> struct BackTile { static constexpr int TP = back_tile_points(L); };
+// LDS padding of the row pass (Geom): PS = 5 measured faster except for the
+// 1024-point FP32 rows.
+template <int L, int PREC> struct BackPad { static constexpr int PS = (PREC == 0 && L == 1024) ? 4 : 5; };
 
 template <int NPOL, int L, int PREC = 0>
 __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
-    typedef Geom<L, BackTile<L>::TP> G;
+    typedef Geom<L, BackTile<L>::TP, BackPad<L, PREC>::PS> G;
     constexpr int NB = G::TPP * NPOL;
     constexpr int NP = NPOL == 2 ? 4 : 1;
     constexpr int BINS = G::TP / NB;

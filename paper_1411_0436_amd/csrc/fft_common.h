@@ -122,13 +122,17 @@ template <> __device__ __forceinline__ void dftR<8>(float2 *v) { dft8(v); }
 // Batched sub-FFT of length L = r0 * 16^n16 over T = TP/L columns per
 // polarisation (TP complex points per polarisation per workgroup step, done by
 // TPP = TP/16 threads, each owning one radix-16 butterfly).  LDS: re and im
-// planes [pol][c][Lp], element e of a column at e + e/16 (one pad word per
-// 16) and one more pad word per column, which keeps the strided pass writes
-// and the column-crossing reads free of bank conflicts.
-template <int L_, int TP_ = kTilePoints>
+// planes [pol][c][Lp], element e of a column at e + (e >> PS) (one pad word
+// per 2^PS) and one more pad word per column.  The 32 four-byte banks serve a
+// wave's access in two halves of 32 lanes, and no single padding makes every
+// access pattern of a kernel conflict-free: PS = 4 suits the column pass, PS
+// = 5 measured faster in the single-pass and most row-pass kernels.  The
+// host sizes LDS for PS = 4, which is the larger.
+template <int L_, int TP_ = kTilePoints, int PS_ = 4>
 struct Geom {
     static constexpr int L = L_;
     static constexpr int TP = TP_;
+    static constexpr int PS = PS_;
     static constexpr int TPP = TP / 16;   // threads per polarisation
     static constexpr int logL = ilog2c(L);
     static constexpr int T = TP / L;
@@ -136,11 +140,12 @@ struct Geom {
     static constexpr int n16 = logL / 4;
     static constexpr int r0 = 1 << (logL % 4);
     static constexpr int L16 = L / 16;
-    static constexpr int Lp = lds_pitch(L);
+    static constexpr int Lp = L + (L >> PS) + 1;
     static constexpr int plane = T * Lp;  // floats of one polarisation plane
     static_assert(T >= 1 && L >= 16, "sub-FFT geometry");
+    static_assert((PS == 4 || PS == 5) && Lp <= lds_pitch(L), "LDS padding within the host's LDS size");
     __device__ __forceinline__ static int idx(int pol, int c, int e) {
-        return (pol * T + c) * Lp + e + (e >> 4);
+        return (pol * T + c) * Lp + e + (e >> PS);
     }
     // Offset of radix-16 pass i in the twiddle table (Ns = r0 * 16^i entries each of 15).
     static constexpr int tw_off(int i) { return i == 0 ? 0 : tw_off(i - 1) + r0 * (1 << (4 * (i - 1))) * 15; }

@@ -15,9 +15,9 @@ constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
 // least 1024 (whole waves per polarisation; 2048 measured slower).
 constexpr int back_tile_points(long long n1) { return n1 < 1024 ? 1024 : (int)n1; }
 
-// LDS words per column of an L-point sub-FFT plane: one pad word per 16
-// elements and one more per column (pads of 0, 3 and 9 words per column
-// measured no better).
+// LDS words allocated per column of an L-point sub-FFT plane: one pad word
+// per 16 elements and one more per column (the larger of the two layouts the
+// kernels use; pads of 0, 3 and 9 words per column measured no better).
 constexpr int lds_pitch(int L) { return L + L / 16 + 1; }
 
 // Runtime view of the batched sub-FFT geometry (the kernels take L as a

@@ -644,7 +644,9 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
             g.fa.ga = p->ga_force > 0 ? p->ga_force : 1;
             g.fa.znt = p->znt;
             g.ba.znt = p->znt;
-            g.na = (int)((ns + g.fa.ga - 1) / g.fa.ga);
+            // items padded to a multiple of 8 for the XCD mapping (the
+            // padding items find their spectra past the range and do nothing)
+            g.na = (int)(((ns + g.fa.ga - 1) / g.fa.ga + 7) / 8 * 8);
             g.ba.ch.gid0 = g0;
             g.ba.jz0 = gjs;
             g.nc = (int)(g1 - g0 + 1);
