@@ -108,7 +108,7 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
             __syncthreads();
         } else {
             // v was read back from LDS, which the next step overwrites
-            if constexpr (FftPrec<PREC>::IN_LDS) __syncthreads();
+            if constexpr (FftPrec<PREC>::IN_LDS || FftWave<G, PREC>::value) __syncthreads();
             if (j0 + c_own < je) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
@@ -404,7 +404,7 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
             }
             __syncthreads();
         } else {
-            if constexpr (FftPrec<PREC>::IN_LDS) __syncthreads();
+            if constexpr (FftPrec<PREC>::IN_LDS || FftWave<G, PREC>::value) __syncthreads();
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
         }

@@ -144,6 +144,8 @@ struct Geom {
     static constexpr int plane = T * Lp;  // floats of one polarisation plane
     static_assert(T >= 1 && L >= 16, "sub-FFT geometry");
     static_assert((PS == 4 || PS == 5) && Lp <= lds_pitch(L), "LDS padding within the host's LDS size");
+    // every column is transformed by lanes of a single wave
+    static constexpr bool WAVE_COLS = L16 <= 64 && TPP % 64 == 0;
     __device__ __forceinline__ static int idx(int pol, int c, int e) {
         return (pol * T + c) * Lp + e + (e >> PS);
     }
@@ -151,29 +153,56 @@ struct Geom {
     static constexpr int tw_off(int i) { return i == 0 ? 0 : tw_off(i - 1) + r0 * (1 << (4 * (i - 1))) * 15; }
 };
 
+// Synchronisation between the passes of a sub-FFT: a workgroup barrier, or,
+// where the lanes of one wave transform each column alone (WAVE), a fence
+// that only keeps the compiler from moving LDS accesses across it: the LDS
+// performs one wave's accesses in program order.
+template <bool WAVE>
+__device__ __forceinline__ void pass_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // First pass, radix R in {2,4,8}, sub-transform size 1 (no twiddle).  Thread
-// lt (0..TPP-1) of polarisation pol does 16/R butterflies.
-template <class G, int R>
+// lt (0..TPP-1) of polarisation pol does 16/R butterflies: with WAVE, those of
+// its own column of the radix-16 passes (bb + s*L/16), else bb + s*TPP
+// counted across the columns.
+template <class G, int R, bool WAVE>
 __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int lt) {
     constexpr int PER = 16 / R;
     constexpr int logLR = G::logL - ilog2c(R);
     constexpr int LR = 1 << logLR;
+    auto butterfly = [&](int s, int &c, int &bb) {
+        if constexpr (WAVE) {
+            c = lt >> (G::logL - 4);
+            bb = (lt & (G::L16 - 1)) + s * G::L16;
+        } else {
+            const int b = lt + s * G::TPP;
+            c = b >> logLR;
+            bb = b & (LR - 1);
+        }
+    };
     float2 v[PER][R];
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-        const int b = lt + s * G::TPP;
-        const int c = b >> logLR, bb = b & (LR - 1);
+        int c, bb;
+        butterfly(s, c, bb);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int a = G::idx(pol, c, bb + r * LR);
             v[s][r] = make_float2(sre[a], sim[a]);
         }
     }
-    __syncthreads();
+    pass_sync<WAVE>();
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-        const int b = lt + s * G::TPP;
-        const int c = b >> logLR, bb = b & (LR - 1);
+        int c, bb;
+        butterfly(s, c, bb);
         dftR<R>(v[s]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -182,13 +211,14 @@ __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int 
             sim[a] = v[s][r].y;
         }
     }
-    __syncthreads();
+    pass_sync<WAVE>();
 }
 
 // Radix-16 pass i (sub-transform size Ns = r0*16^i): butterfly bb of column c
 // reads elements bb + r*L/16, applies W_(16 Ns)^(k r) with k = bb mod Ns, and
-// (except in the last pass) writes element (bb-k)*16 + k + r*Ns.
-template <class G, int I>
+// (except in the last pass) writes element (bb-k)*16 + k + r*Ns.  With WAVE
+// the last pass ends without a barrier.
+template <class G, int I, bool WAVE>
 __device__ __forceinline__ void pass16(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                        float2 (&v)[16]) {
     constexpr int Ns = G::r0 * (1 << (4 * I));
@@ -206,7 +236,7 @@ __device__ __forceinline__ void pass16(float *sre, float *sim, int pol, int lt, 
         const int a = G::idx(pol, c, bb + r * G::L16);
         v[r] = make_float2(sre[a], sim[a]);
     }
-    __syncthreads();
+    if (!(WAVE && LAST)) pass_sync<WAVE>();
     if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
@@ -220,26 +250,30 @@ __device__ __forceinline__ void pass16(float *sre, float *sim, int pol, int lt, 
             sre[a] = v[r].x;
             sim[a] = v[r].y;
         }
-        __syncthreads();
+        pass_sync<WAVE>();
     }
 }
 
-template <class G, int I>
+template <class G, int I, bool WAVE>
 __device__ __forceinline__ void passes16(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                          float2 (&v)[16]) {
-    pass16<G, I>(sre, sim, pol, lt, tw, v);
-    if constexpr (I + 1 < G::n16) passes16<G, I + 1>(sre, sim, pol, lt, tw, v);
+    pass16<G, I, WAVE>(sre, sim, pol, lt, tw, v);
+    if constexpr (I + 1 < G::n16) passes16<G, I + 1, WAVE>(sre, sim, pol, lt, tw, v);
 }
 
 // Whole batched FFT of the columns of one polarisation plane held in LDS.
 // On return thread lt holds X_c[bb + r*L/16], r = 0..15, with
 // c = lt / (L/16), bb = lt mod (L/16).  Every thread of the workgroup must
-// call it (it contains workgroup barriers).
-template <class G>
+// call it.  Without WAVE it contains workgroup barriers and ends with one;
+// with WAVE (G::WAVE_COLS) the passes synchronise within each wave only, and
+// on return other waves may still be reading the plane: a thread may then
+// overwrite only the positions it holds in v until a workgroup barrier.
+template <class G, bool WAVE = false>
 __device__ __forceinline__ void fft_plane(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                           float2 (&v)[16]) {
-    if constexpr (G::r0 > 1) pass_small<G, G::r0>(sre, sim, pol, lt);
-    passes16<G, 0>(sre, sim, pol, lt, tw, v);
+    static_assert(!WAVE || G::WAVE_COLS, "wave-local passes need columns within one wave");
+    if constexpr (G::r0 > 1) pass_small<G, G::r0, WAVE>(sre, sim, pol, lt);
+    passes16<G, 0, WAVE>(sre, sim, pol, lt, tw, v);
 }
 
 // ------------------------------------------------- matrix-core radix 16 --
@@ -388,20 +422,22 @@ template <class G, int PREC>
 __device__ __forceinline__ void fft_plane_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                                const MfmaW &W) {
     static_assert(G::TPP % 64 == 0, "whole waves per polarisation");
-    if constexpr (G::r0 > 1) pass_small<G, G::r0>(sre, sim, pol, lt);
+    if constexpr (G::r0 > 1) pass_small<G, G::r0, false>(sre, sim, pol, lt);
     passes16_mfma<G, 0, PREC>(sre, sim, pol, lt, tw, W);
 }
 
 // Precision dispatch: on return thread lt holds X_c[bb + r*L/16] in v (as
 // fft_plane), and with IN_LDS the whole transform is also in LDS in natural
-// order (matrix-core passes only).
+// order (matrix-core passes only).  WAVE: the FP32 passes synchronise per
+// wave where the geometry allows it (see fft_plane).
 template <int PREC> struct FftPrec { static constexpr bool IN_LDS = PREC != 0; };
+template <class G, int PREC> struct FftWave { static constexpr bool value = PREC == 0 && G::WAVE_COLS; };
 
 template <class G, int PREC>
 __device__ __forceinline__ void fft_plane_p(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                             const MfmaW &W, float2 (&v)[16], bool want_regs) {
     if constexpr (PREC == 0) {
-        fft_plane<G>(sre, sim, pol, lt, tw, v);
+        fft_plane<G, FftWave<G, PREC>::value>(sre, sim, pol, lt, tw, v);
     } else {
         fft_plane_mfma<G, PREC>(sre, sim, pol, lt, tw, W);
         if (want_regs) {
