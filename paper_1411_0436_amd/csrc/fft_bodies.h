@@ -308,6 +308,143 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     }
 }
 
+// Column pass with pre-filter, FP32, two consecutive spectra j and j+1 per
+// workgroup step (twice the threads and LDS of front_cols_body).  The
+// pre-filter reads most of its bytes from L2 (P frames and P tap rows per
+// point), so each thread filters its points for both spectra at once: one
+// load of tap row p serves both, and the frames slide (frame j+p+1 is the
+// second spectrum's tap p and the first's tap p+1), P+2 frame loads for two
+// spectra instead of 2P.  Each half of the workgroup then transforms and
+// stores one spectrum, exactly as front_cols_body does (same arithmetic in
+// the same order, so the same bits).
+template <int NPOL, int L>
+__device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid, int nblk) {
+    typedef Geom<L> G;
+    typedef typename Sample<NPOL>::word W;
+    typedef typename Sample<NPOL>::word4 W4;
+    constexpr int NB = G::TPP * NPOL;   // threads per spectrum
+    constexpr int GRP = G::TP / (8 * NB);  // 4-point groups per thread and spectrum
+    static_assert(G::T % 4 == 0 && GRP >= 1 && GRP * 8 * NB == G::TP, "pair tile of whole 4-sample groups");
+    extern __shared__ float smem[];
+    const int tid = threadIdx.x, half = tid / NB, t = tid - half * NB;
+    const int pol = t / G::TPP, lt = t % G::TPP;
+    float *sre = smem + half * (2 * NPOL * G::plane);
+    float *sim = sre + NPOL * G::plane;
+    int tile, item;
+    cols_tile_item<G::T, NPOL>(a.ntiles, bid, nblk, tile, item);
+    // spectra [js, je): the item-th run of 2*ga spectra of the launch's range
+    const long long js = a.sa0 + (long long)item * 2 * a.ga;
+    const long long je = min(js + 2LL * a.ga, a.sa1);
+    const long long N = a.N;
+    const int N1 = (int)a.N1;
+    const int n1_0 = tile * G::T;
+    const int P = a.P;
+    const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
+    const float2 *tw4 = a.tw4 + (unsigned)((n1_0 + c_own) * L + bb_own);
+    MfmaW Wm{};
+
+    for (long long j = js; j < je; j += 2) {
+        const bool two = j + 1 < je;
+        // last frame read by a spectrum of this step (reads past it are
+        // clamped to it and their results unused)
+        const long long f_last = j + (two ? 1 : 0) + P - 1;
+        float2 y[2][4 * GRP][NPOL];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int s = 0; s < 4 * GRP; ++s)
+#pragma unroll
+                for (int pp = 0; pp < NPOL; ++pp) y[h][s][pp] = make_float2(0.f, 0.f);
+        auto frame_loads = [&](long long f, W4 (&w4)[GRP]) {
+            const W *fb = frame_ptr<NPOL>(a.fr, min(f, f_last), N) + n1_0;
+#pragma unroll
+            for (int g = 0; g < GRP; ++g) {
+                const int q = tid + 2 * NB * g;
+                const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
+                w4[g] = *reinterpret_cast<const W4 *>(fb + n);
+            }
+        };
+        auto tap_loads = [&](int p, float4 (&h4)[GRP]) {
+            const float *hb = a.taps + (long long)p * N + n1_0;
+#pragma unroll
+            for (int g = 0; g < GRP; ++g) {
+                const int q = tid + 2 * NB * g;
+                const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
+                h4[g] = *reinterpret_cast<const float4 *>(hb + n);
+            }
+        };
+        // xa: frame j+p (first spectrum's tap p), xb: frame j+p+1 (second's)
+        W4 xa[GRP], xb[GRP];
+        float4 h4[GRP];
+        frame_loads(j, xa);
+        frame_loads(j + 1, xb);
+        tap_loads(0, h4);
+        for (int p = 0; p < P; ++p) {
+            // next step's loads before this step's arithmetic
+            W4 xn[GRP];
+            float4 hn[GRP];
+            frame_loads(j + p + 2, xn);
+            tap_loads(min(p + 1, P - 1), hn);
+#pragma unroll
+            for (int g = 0; g < GRP; ++g) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    tap_fma<NPOL>(y[0][4 * g + e], part4(h4[g], e), Sample<NPOL>::part(xa[g], e));
+                    tap_fma<NPOL>(y[1][4 * g + e], part4(h4[g], e), Sample<NPOL>::part(xb[g], e));
+                }
+                xa[g] = xb[g];
+                xb[g] = xn[g];
+                h4[g] = hn[g];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float *hre = smem + h * (2 * NPOL * G::plane), *him = hre + NPOL * G::plane;
+#pragma unroll
+            for (int g = 0; g < GRP; ++g) {
+                const int q = tid + 2 * NB * g;
+                const int c0 = 4 * (q & (G::T / 4 - 1)), n2 = q >> (G::logT - 2);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int pp = 0; pp < NPOL; ++pp) {
+                        const int ad = G::idx(pp, c0 + e, n2);
+                        hre[ad] = y[h][4 * g + e][pp].x;
+                        him[ad] = y[h][4 * g + e][pp].y;
+                    }
+            }
+        }
+        __syncthreads();
+        float2 v[16];
+        fft_plane_p<G, 0>(sre, sim, pol, lt, a.g.tw, Wm, v, true);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int k2 = bb_own + r * G::L16;
+            const float2 z = cmul(v[r], tw4[r * G::L16]);
+            const int ad = G::idx(pol, c_own, k2);
+            sre[ad] = z.x;
+            sim[ad] = z.y;
+        }
+        __syncthreads();
+        if (half == 0 || two) {
+            float2 *zb = a.Z + (j + half - a.jz0) * NPOL * N + n1_0;
+#pragma unroll
+            for (int s = 0; s < (NPOL * G::TP) / (2 * NB); ++s) {
+                const int i = t + NB * s;
+                const int cc = 2 * (i & (G::T / 2 - 1));
+                const int k2 = (i >> (G::logT - 1)) & (L - 1);
+                const int pp = i >> (G::logT - 1 + G::logL);
+                const int ad0 = G::idx(pp, cc, k2), ad1 = G::idx(pp, cc + 1, k2);
+                const floatx4 v = {sre[ad0], sim[ad0], sre[ad1], sim[ad1]};
+                floatx4 *zp = reinterpret_cast<floatx4 *>(zb + (unsigned)(pp * (int)N + k2 * N1 + cc));
+                if (a.znt) __builtin_nontemporal_store(v, zp);
+                else *zp = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Row-pass tile: at least 1024 points per polarisation (64 threads each), so
 // short rows still give many small workgroups.
 template <int L> struct BackTile { static constexpr int TP = back_tile_points(L); };

@@ -20,6 +20,11 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL, (ColsMinWaves<L, PREC>::va
     front_cols_body<NPOL, PFB, L, PREC>(a, blockIdx.x, gridDim.x);
 }
 
+template <int NPOL, int L>
+__global__ __launch_bounds__(kTilePoints / 16 * NPOL * 2) void k_front_cols_pair(FrontArgs a) {
+    front_cols_pair_body<NPOL, L>(a, blockIdx.x, gridDim.x);
+}
+
 template <int NPOL, int L, int PREC>
 __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a) {
     back_body<NPOL, L, PREC>(a, blockIdx.x);
@@ -94,6 +99,22 @@ hipError_t init_fourstep_p(int lds_limit) {
 hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, int n_items, hipStream_t s) {
     const size_t lds = front_lds_bytes(a.g, npol);
     const dim3 grid(n_items * a.ntiles), block(kTilePoints / 16 * npol);
+    if (a.pair) {
+        if (prec != 0 || !pfb) return hipErrorInvalidValue;
+        const dim3 block2(2 * block.x);
+        switch (a.g.L) {
+#define PFBS_CASE(LL)                                                                                \
+    case LL:                                                                                         \
+        if (npol == 2) PFBS_LAUNCH((k_front_cols_pair<2, LL>), grid, block2, 2 * lds, s, a); \
+        else PFBS_LAUNCH((k_front_cols_pair<1, LL>), grid, block2, 2 * lds, s, a);           \
+        break;
+            PFBS_COLS_CASES(PFBS_CASE)
+#undef PFBS_CASE
+        default:
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (prec) {
     case 0: return launch_cols_p<0>(a, npol, pfb, grid, block, lds, s);
     case 1: return launch_cols_p<1>(a, npol, pfb, grid, block, lds, s);
@@ -117,6 +138,18 @@ hipError_t init_fourstep(int lds_limit) {
     hipError_t e0 = init_fourstep_p<0>(lds_limit), e1 = init_fourstep_p<1>(lds_limit),
                e2 = init_fourstep_p<2>(lds_limit);
     return e0 != hipSuccess ? e0 : (e1 != hipSuccess ? e1 : e2);
+}
+
+bool init_fourstep_pair(int lds_limit) {
+    bool ok = true;
+#define PFBS_CASE(LL)                                                                                           \
+    for (const void *fn : {reinterpret_cast<const void *>(k_front_cols_pair<2, LL>),                              \
+                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL>)})                             \
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess) ok = false;
+    PFBS_COLS_CASES(PFBS_CASE)
+#undef PFBS_CASE
+    (void)hipGetLastError();
+    return ok;
 }
 
 }  // namespace pfbs

@@ -61,6 +61,7 @@ struct FrontArgs {
     long long sa0, sa1;
     int ga;
     int znt;                  // 1: streaming (non-temporal) stores of Z
+    int pair;                 // 1: two spectra per workgroup step (runs of 2*ga)
     float2 *Z;                // [spectra of launch][pol][N2][N1]
     long long jz0;            // spectrum index of Z[0]
     const float2 *tw4;        // [n1][k2] = W_N^(n1*k2), N entries
@@ -179,6 +180,7 @@ hipError_t launch_history(uint8_t *dst, const Frames &fr, long long F, int H, lo
 hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long long N, int P,
                             int npol, bool pfb, long long j_lo, long long j_hi, hipStream_t s);
 hipError_t kernels_init();   // raise LDS limits once per process/device
+bool init_fourstep_pair(int lds_limit);  // LDS limit of the two-spectra column kernels; false if refused
 size_t front_lds_bytes(const Geo &g, int npol);
 size_t back_lds_bytes(const Geo &g, int npol);
 

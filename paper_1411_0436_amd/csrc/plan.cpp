@@ -84,6 +84,10 @@ int64_t tw16_count(const Geo &g) {
 
 std::mutex g_init_mu;
 bool g_init_done[64];
+// Column pass on two spectra per workgroup step: its LDS (twice the one-spectrum
+// kernel's, up to 140 KB) is available on the device.
+bool g_pair_ok[64];
+constexpr int kPairLds = 160 * 1024;
 
 }  // namespace
 
@@ -108,6 +112,7 @@ struct pfbs_plan {
     int ga_force;        // column-pass spectra per workgroup (0 = automatic)
     int out_stokes, out_shift;  // dump form: Stokes parameters, shifted channel order
     int znt;             // streaming stores/loads of the four-step intermediate
+    bool pair;           // FP32 pre-filter column pass on two spectra per workgroup step
     // device state
     float *taps;
     float2 *twA, *twB, *tw4;
@@ -349,6 +354,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
         if (!g_init_done[dev]) {
             hipError_t e = kernels_init();
             if (e != hipSuccess) return hip_fail(nullptr, e, "kernel attributes");
+            g_pair_ok[dev] = init_fourstep_pair(kPairLds);
             g_init_done[dev] = true;
         }
     }
@@ -400,6 +406,13 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->frame_bytes = p->N * 2 * p->npol;
     p->ga_force = desc->col_run;
     p->znt = desc->stream_z;
+    // Two spectra per column-pass step share each tap-row load: measured
+    // faster only where the tap table (P*N floats) overflows the 4 MB L2 of
+    // an XCD (N = 2^19: column pass -8%; N <= 2^16: +3 to +6%), and with
+    // columns of at most 256 (the 512 kernel spills registers).
+    p->pair = p->fourstep && p->pfb && p->prec_front == PFBS_PREC_FP32 && g_pair_ok[dev] &&
+              p->gA.L <= 256 && (int64_t)p->P * p->N >= (int64_t(1) << 21) &&
+              2 * front_lds_bytes(p->gA, p->npol) <= (size_t)kPairLds;
     p->out_stokes = desc->output == PFBS_OUT_STOKES;
     p->out_shift = desc->fftshift;
 
@@ -644,9 +657,12 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
             g.fa.ga = p->ga_force > 0 ? p->ga_force : 1;
             g.fa.znt = p->znt;
             g.ba.znt = p->znt;
+            // batches (one_group) run the one-spectrum column kernel
+            g.fa.pair = p->pair && !one_group;
+            const int64_t run = (int64_t)g.fa.ga * (g.fa.pair ? 2 : 1);
             // items padded to a multiple of 8 for the XCD mapping (the
             // padding items find their spectra past the range and do nothing)
-            g.na = (int)(((ns + g.fa.ga - 1) / g.fa.ga + 7) / 8 * 8);
+            g.na = (int)(((ns + run - 1) / run + 7) / 8 * 8);
             g.ba.ch.gid0 = g0;
             g.ba.jz0 = gjs;
             g.nc = (int)(g1 - g0 + 1);
