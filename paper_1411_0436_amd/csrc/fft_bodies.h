@@ -448,9 +448,9 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
 // Row-pass tile: at least 1024 points per polarisation (64 threads each), so
 // short rows still give many small workgroups.
 template <int L> struct BackTile { static constexpr int TP = back_tile_points(L); };
-// LDS padding of the row pass (Geom): PS = 5 measured faster except for the
-// 1024-point FP32 rows.
-template <int L, int PREC> struct BackPad { static constexpr int PS = (PREC == 0 && L == 1024) ? 4 : 5; };
+// LDS padding of the row pass (Geom): PS = 5 measured faster except for FP32
+// rows of 512 points and more (N = 2^17: row pass 0.113 -> 0.093 ms with PS = 4).
+template <int L, int PREC> struct BackPad { static constexpr int PS = (PREC == 0 && L >= 512) ? 4 : 5; };
 
 template <int NPOL, int L, int PREC = 0>
 __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
