@@ -478,9 +478,47 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) acc[i][q] = 0.f;
 
+    // FP32 rows shorter than 1024: the next spectrum's intermediate is loaded
+    // into registers while this one is transformed (two consecutive n1, 16
+    // bytes, per access)
+    constexpr bool ZPRE = PREC == 0 && L < 1024;
+    constexpr int NZ = (NPOL * G::TP) / (2 * NB);
+    auto z_loads = [&](long long jj, floatx4 (&z)[NZ]) {
+        const float2 *zb = a.Z + (jj - a.jz0) * NPOL * N + (long long)k2_0 * L;
+#pragma unroll
+        for (int s = 0; s < NZ; ++s) {
+            const int i = tid + NB * s;
+            const int n1 = 2 * (i & (L / 2 - 1));
+            const int cc = (i >> (G::logL - 1)) & (G::T - 1);
+            const int pp = i >> (G::logL - 1 + G::logT);
+            const floatx4 *zp = reinterpret_cast<const floatx4 *>(zb + (unsigned)(pp * (int)N + cc * L + n1));
+            z[s] = a.znt ? __builtin_nontemporal_load(zp) : *zp;
+        }
+    };
+    auto z_to_lds = [&](const floatx4 (&z)[NZ]) {
+#pragma unroll
+        for (int s = 0; s < NZ; ++s) {
+            const int i = tid + NB * s;
+            const int n1 = 2 * (i & (L / 2 - 1));
+            const int cc = (i >> (G::logL - 1)) & (G::T - 1);
+            const int pp = i >> (G::logL - 1 + G::logT);
+            const int ad0 = G::idx(pp, cc, n1), ad1 = G::idx(pp, cc, n1 + 1);
+            sre[ad0] = z[s][0];
+            sim[ad0] = z[s][1];
+            sre[ad1] = z[s][2];
+            sim[ad1] = z[s][3];
+        }
+    };
+    floatx4 zc[ZPRE ? NZ : 1];
+    if constexpr (ZPRE) {
+        if (js < je) z_loads(js, zc);
+    }
+
     for (long long j = js; j < je; ++j) {
         const float2 *zb = a.Z + (j - a.jz0) * NPOL * N + (long long)k2_0 * L;
-        if constexpr (L >= 1024) {
+        if constexpr (ZPRE) {
+            z_to_lds(zc);
+        } else if constexpr (L >= 1024) {
             // one complex value per access: consecutive lanes write
             // consecutive LDS words (the paired form below halves the
             // accesses but doubles the LDS bank conflicts of long rows)
@@ -520,6 +558,9 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
             }
         }
         __syncthreads();
+        if constexpr (ZPRE) {
+            if (j + 1 < je) z_loads(j + 1, zc);
+        }
         float2 v[16];
         fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, NPOL == 1);
         if constexpr (NPOL == 2) {
