@@ -1014,8 +1014,10 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             // to the 8 XCDs round-robin and the column pass maps its tiles to
             // XCDs by block id
             wg += (E.wgn + 7) & ~7;
-            wg_max += (int)((v.kind == 0 ? max_chunks(p, F)
-                                         : p->ntilesA * ((F + std::max(1, p->ga_force) - 1) / std::max(1, p->ga_force))) + 7) & ~7;
+            // upper bound for the captured graph: the column pass's item count
+            // is padded to a multiple of 8 (as in prepare)
+            const int64_t ga = std::max(1, p->ga_force);
+            wg_max += (int)((v.kind == 0 ? max_chunks(p, F) : p->ntilesA * (((F + ga - 1) / ga + 7) / 8 * 8)) + 7) & ~7;
             lds = std::max(lds, front_lds_bytes(p->gA, p->npol));
         }
         LF.push_back({multi_front_fn(b->npol, v.kind, v.pfb, v.L), use_graph ? wg_max : wg,

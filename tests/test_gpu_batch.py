@@ -111,3 +111,32 @@ def test_two_spectra_column_kernel_bitwise():
     assert got.shape == want.shape and want.shape[0] == (5 + 11 + 10) // ni
     assert np.array_equal(got, want)
     assert bcnt == cnt and np.array_equal(bpart.cpu().numpy(), part)
+
+
+def test_graph_grid_covers_padded_column_items():
+    """The captured graph launches the column pass with an upper-bound grid;
+    it must cover the item count padded to a multiple of 8 per column tile
+    (blocks of 9 and 13 frames: 2, 9 and 13 spectra, 4 and 16 tiles)."""
+    torch = require_gpu()
+    subs = [(16384, 8, pf.MODE_PFB, 3), (65536, 4, pf.MODE_PFB, 2)]
+    frames = [9, 13, 9]
+    xs = [synth.generate(synth.spec_subband(s, N), 3, N * sum(frames)) for s, (N, *_r) in enumerate(subs)]
+    b = pf.Batch([pf.make_desc(N=N, P=P, mode=m, n_pol=2, n_int=ni) for (N, P, m, ni) in subs])
+    got = [[] for _ in subs]
+    pos = [0] * len(subs)
+    for f in frames:
+        blocks, dumps = [], []
+        for i, (N, *_r) in enumerate(subs):
+            blocks.append(torch.from_numpy(np.ascontiguousarray(xs[i][pos[i]:pos[i] + f * N])).cuda())
+            pos[i] += f * N
+            dumps.append(torch.empty((max(b.plans[i].dumps_in(f * N), 1), 4, N), dtype=torch.float32, device="cuda"))
+        nd = b.execute(blocks, dumps, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(subs)):
+            if nd[i]:
+                got[i].append(dumps[i][:nd[i]].cpu().numpy())
+    b.close()
+    for i, (N, P, m, ni) in enumerate(subs):
+        want, _part, _cnt = run_stream(pf.Plan(N, P, mode=m, n_pol=2, n_int=ni), xs[i], frames)
+        g = np.concatenate(got[i])
+        assert g.shape == want.shape and np.array_equal(g, want), i
