@@ -81,7 +81,8 @@ def test_batched_graph_replays_match_oracle():
             assert within_fp32_bound(got[i][d], ref[d], N) <= 1.0, (i, d)
 
 
-def test_two_spectra_column_kernel_bitwise():
+@pytest.mark.parametrize("n_pol", [2, 1])
+def test_two_spectra_column_kernel_bitwise(n_pol):
     """Where the tap table is large (P*N >= 2^21 floats) a plan's FP32 column
     pass filters two spectra per workgroup step; batches run the one-spectrum
     kernel.  Both do the same arithmetic in the same order, so one sub-band
@@ -91,19 +92,22 @@ def test_two_spectra_column_kernel_bitwise():
     N, P, ni = 262144, 8, 3
     frames = [12, 11, 10]
     x = synth.generate(synth.spec_subband(5, N), 7, N * sum(frames))
-    kw = dict(N=N, P=P, mode=pf.MODE_PFB, n_pol=2, n_int=ni, split_n2=256)
+    if n_pol == 1:
+        x = np.ascontiguousarray(x[:, :1, :])
+    kw = dict(N=N, P=P, mode=pf.MODE_PFB, n_pol=n_pol, n_int=ni, split_n2=256)
     want, part, cnt = run_stream(pf.Plan(**kw), x, frames)
     b = pf.Batch([pf.make_desc(**kw)])
     got, pos = [], 0
     for f in frames:
         blk = torch.from_numpy(np.ascontiguousarray(x[pos:pos + f * N])).cuda()
         pos += f * N
-        d = torch.empty((max(b.plans[0].dumps_in(f * N), 1), 4, N), dtype=torch.float32, device="cuda")
+        d = torch.empty((max(b.plans[0].dumps_in(f * N), 1), 4 if n_pol == 2 else 1, N), dtype=torch.float32,
+                        device="cuda")
         nd = b.execute([blk], [d])
         torch.cuda.synchronize()
         if nd[0]:
             got.append(d[:nd[0]].cpu().numpy())
-    bpart = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    bpart = torch.empty((4 if n_pol == 2 else 1, N), dtype=torch.float32, device="cuda")
     bcnt = b.plans[0].flush(bpart)
     torch.cuda.synchronize()
     b.close()
