@@ -18,11 +18,13 @@ hipError_t init_fourstep(int lds_limit);
 // chunk order.  Complete dumps go to out in channel order; an incomplete one
 // (only the last) to carried_out, a different buffer from carried_in because
 // the first dump of the same launch may still be reading that one.
-// Four-step order (N2 > 1): a workgroup takes 8 k2 x 32 k1 (reads along k1,
-// one partial per thread), then writes channel order k = k2 + N2 k1 through
-// LDS.  Single pass (N2 == 1): 256 consecutive channels.
+// Four-step order (N2 > 1): a workgroup takes 32 k2 x 32 k1, four per thread
+// (reads along k1: 128-byte rows of the partials), then writes channel order
+// k = k2 + N2 k1 through LDS (128-byte rows along k2).  Single pass
+// (N2 == 1): 256 consecutive channels.
+constexpr int kReduceTile = 32;
 __device__ void reduce_body(const ReduceArgs &a, int bx, int by, int bz) {
-    __shared__ float tile[8][33];
+    __shared__ float tile[kReduceTile][kReduceTile + 1];
     const int t = threadIdx.x;
     const long long d = a.d_lo + by;
     const int q = bz;
@@ -33,44 +35,51 @@ __device__ void reduce_body(const ReduceArgs &a, int bx, int by, int bz) {
     const long long slot = d - a.d_lo;
     const long long N = a.N;
     const bool tr = a.N2 > 1;
-    long long u;
+    constexpr int R = kReduceTile * kReduceTile / 256;  // elements per thread (four-step)
+    const int nel = tr ? R : 1;
     long long k2b = 0, k1b = 0;
     if (tr) {
-        const long long nt2 = a.N2 / 8;
-        k2b = (bx % nt2) * 8;
-        k1b = (bx / nt2) * 32;
-        u = (k2b + (t >> 5)) * a.N1 + k1b + (t & 31);
-    } else {
-        u = (long long)bx * 256 + t;
+        const long long nt2 = a.N2 / kReduceTile;
+        k2b = (bx % nt2) * kReduceTile;
+        k1b = (bx / nt2) * kReduceTile;
     }
-    float s = 0.f;
-    if (u < N) {
-        if (carried_in) s = a.carried_in[q * N + u];
-        if (!a.flush) {
-            const float *pp = a.part + q * N + u;
-            const long long stride = (long long)a.n_prod * N;
-            long long gg = g_first;
-            // batches of independent loads, added in chunk order
-            for (; gg + 8 <= g_last + 1; gg += 8) {
-                float v[8];
+    float sv[R];
+    for (int e = 0; e < nel; ++e) {
+        const int row = (t >> 5) + 8 * e;  // k2 offset of this element (four-step)
+        const long long u = tr ? (k2b + row) * a.N1 + k1b + (t & 31) : (long long)bx * 256 + t;
+        float s = 0.f;
+        if (u < N) {
+            if (carried_in) s = a.carried_in[q * N + u];
+            if (!a.flush) {
+                const float *pp = a.part + q * N + u;
+                const long long stride = (long long)a.n_prod * N;
+                long long gg = g_first;
+                // batches of independent loads, added in chunk order
+                for (; gg + 8 <= g_last + 1; gg += 8) {
+                    float v[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) v[i] = pp[(gg + i - a.gid_lo) * stride];
+                    for (int i = 0; i < 8; ++i) v[i] = pp[(gg + i - a.gid_lo) * stride];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) s += v[i];
+                    for (int i = 0; i < 8; ++i) s += v[i];
+                }
+                for (; gg <= g_last; ++gg) s += pp[(gg - a.gid_lo) * stride];
             }
-            for (; gg <= g_last; ++gg) s += pp[(gg - a.gid_lo) * stride];
+            if (!complete) a.carried_out[q * N + u] = s;
         }
-        if (!complete) a.carried_out[q * N + u] = s;
+        sv[e] = s;
     }
     if (!complete) return;
     float *out = a.out + (slot * a.n_prod + q) * N;
     if (tr) {
-        tile[t >> 5][t & 31] = s;
+        for (int e = 0; e < R; ++e) tile[(t >> 5) + 8 * e][t & 31] = sv[e];
         __syncthreads();
-        const int dk2 = t & 7, dk1 = t >> 3;
-        out[(k2b + dk2) + a.N2 * (k1b + dk1)] = tile[dk2][dk1];
-    } else if (u < N) {
-        out[u] = s;
+        for (int e = 0; e < R; ++e) {
+            const int dk2 = t & 31, dk1 = (t >> 5) + 8 * e;
+            out[(k2b + dk2) + a.N2 * (k1b + dk1)] = tile[dk2][dk1];
+        }
+    } else {
+        const long long u = (long long)bx * 256 + t;
+        if (u < N) out[u] = sv[0];
     }
 }
 
@@ -311,7 +320,7 @@ hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s) {
     if (n_dumps <= 0) return hipSuccess;
     const unsigned gy = (unsigned)std::min(n_dumps, 65535);
     dim3 grid;
-    if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / 8) * (a.N1 / 32)), gy, (unsigned)a.n_prod);
+    if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / kReduceTile) * (a.N1 / kReduceTile)), gy, (unsigned)a.n_prod);
     else grid = dim3((unsigned)((a.N + 255) / 256), gy, (unsigned)a.n_prod);
     PFBS_LAUNCH(k_reduce, grid, dim3(256), 0, s, a, n_dumps);
     return hipGetLastError();

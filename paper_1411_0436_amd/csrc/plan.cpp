@@ -877,7 +877,7 @@ struct BLaunch {
 int64_t max_chunks(const pfbs_plan *p, int64_t F) { return F / p->G + F / p->n_int + 3; }
 int64_t max_dumps(const pfbs_plan *p, int64_t F) { return F / p->n_int + 2; }
 int reduce_gx(const pfbs_plan *p) {
-    return p->fourstep ? (int)((p->N2 / 8) * (p->N1 / 32)) : (int)((p->N + 255) / 256);
+    return p->fourstep ? (int)((p->N2 / 32) * (p->N1 / 32)) : (int)((p->N + 255) / 256);  // k_reduce tiles
 }
 int hist_wg(const pfbs_plan *p) {
     return (int)std::min<int64_t>(1024, ((int64_t)(p->P - 1) * (p->frame_bytes / 16) + 255) / 256);
