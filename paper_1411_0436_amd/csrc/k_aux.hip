@@ -23,8 +23,39 @@ hipError_t init_fourstep(int lds_limit);
 // k = k2 + N2 k1 through LDS (128-byte rows along k2).  Single pass
 // (N2 == 1): 256 consecutive channels.
 constexpr int kReduceTile = 32;
+
+// s[e] = carried-in value (if any) + the chunk partials in chunk order, for NE
+// elements at offsets u[e]; the elements' loads go out together (eight chunks
+// at a time) so that one thread keeps 8*NE loads in flight.
+template <int NE>
+__device__ __forceinline__ void reduce_sums(const ReduceArgs &a, int q, bool carried_in, long long g_first,
+                                            long long g_last, const long long (&u)[NE], float (&s)[NE]) {
+    const long long N = a.N;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) s[e] = carried_in ? a.carried_in[q * N + u[e]] : 0.f;
+    if (a.flush) return;
+    const long long stride = (long long)a.n_prod * N;
+    const float *pp = a.part + q * N;
+    long long gg = g_first;
+    for (; gg + 8 <= g_last + 1; gg += 8) {
+        float v[8][NE];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) v[i][e] = pp[(gg + i - a.gid_lo) * stride + u[e]];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) s[e] += v[i][e];
+    }
+    for (; gg <= g_last; ++gg)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) s[e] += pp[(gg - a.gid_lo) * stride + u[e]];
+}
+
 __device__ void reduce_body(const ReduceArgs &a, int bx, int by, int bz) {
     __shared__ float tile[kReduceTile][kReduceTile + 1];
+    constexpr int R = kReduceTile * kReduceTile / 256;  // elements per thread (four-step)
     const int t = threadIdx.x;
     const long long d = a.d_lo + by;
     const int q = bz;
@@ -34,52 +65,36 @@ __device__ void reduce_body(const ReduceArgs &a, int bx, int by, int bz) {
     const bool complete = a.flush ? true : ((d + 1) * a.n_int <= a.j_hi);
     const long long slot = d - a.d_lo;
     const long long N = a.N;
-    const bool tr = a.N2 > 1;
-    constexpr int R = kReduceTile * kReduceTile / 256;  // elements per thread (four-step)
-    const int nel = tr ? R : 1;
-    long long k2b = 0, k1b = 0;
-    if (tr) {
-        const long long nt2 = a.N2 / kReduceTile;
-        k2b = (bx % nt2) * kReduceTile;
-        k1b = (bx / nt2) * kReduceTile;
-    }
-    float sv[R];
-    for (int e = 0; e < nel; ++e) {
-        const int row = (t >> 5) + 8 * e;  // k2 offset of this element (four-step)
-        const long long u = tr ? (k2b + row) * a.N1 + k1b + (t & 31) : (long long)bx * 256 + t;
-        float s = 0.f;
-        if (u < N) {
-            if (carried_in) s = a.carried_in[q * N + u];
-            if (!a.flush) {
-                const float *pp = a.part + q * N + u;
-                const long long stride = (long long)a.n_prod * N;
-                long long gg = g_first;
-                // batches of independent loads, added in chunk order
-                for (; gg + 8 <= g_last + 1; gg += 8) {
-                    float v[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) v[i] = pp[(gg + i - a.gid_lo) * stride];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) s += v[i];
-                }
-                for (; gg <= g_last; ++gg) s += pp[(gg - a.gid_lo) * stride];
-            }
-            if (!complete) a.carried_out[q * N + u] = s;
-        }
-        sv[e] = s;
-    }
-    if (!complete) return;
     float *out = a.out + (slot * a.n_prod + q) * N;
-    if (tr) {
+    if (a.N2 > 1) {
+        const long long nt2 = a.N2 / kReduceTile;
+        const long long k2b = (bx % nt2) * kReduceTile, k1b = (bx / nt2) * kReduceTile;
+        long long u[R];
+        float sv[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) u[e] = (k2b + (t >> 5) + 8 * e) * a.N1 + k1b + (t & 31);
+        reduce_sums<R>(a, q, carried_in, g_first, g_last, u, sv);
+        if (!complete) {
+#pragma unroll
+            for (int e = 0; e < R; ++e) a.carried_out[q * N + u[e]] = sv[e];
+            return;
+        }
+#pragma unroll
         for (int e = 0; e < R; ++e) tile[(t >> 5) + 8 * e][t & 31] = sv[e];
         __syncthreads();
+#pragma unroll
         for (int e = 0; e < R; ++e) {
             const int dk2 = t & 31, dk1 = (t >> 5) + 8 * e;
             out[(k2b + dk2) + a.N2 * (k1b + dk1)] = tile[dk2][dk1];
         }
     } else {
-        const long long u = (long long)bx * 256 + t;
-        if (u < N) out[u] = sv[0];
+        const long long u0 = (long long)bx * 256 + t;
+        if (u0 >= N) return;
+        const long long u[1] = {u0};
+        float sv[1];
+        reduce_sums<1>(a, q, carried_in, g_first, g_last, u, sv);
+        if (!complete) a.carried_out[q * N + u0] = sv[0];
+        else out[u0] = sv[0];
     }
 }
 
