@@ -478,10 +478,9 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) acc[i][q] = 0.f;
 
-    // FP32 rows shorter than 1024: the next spectrum's intermediate is loaded
-    // into registers while this one is transformed (two consecutive n1, 16
-    // bytes, per access)
-    constexpr bool ZPRE = PREC == 0 && L < 1024;
+    // FP32 rows: the next spectrum's intermediate is loaded into registers
+    // while this one is transformed (two consecutive n1, 16 bytes, per access)
+    constexpr bool ZPRE = PREC == 0;
     constexpr int NZ = (NPOL * G::TP) / (2 * NB);
     auto z_loads = [&](long long jj, floatx4 (&z)[NZ]) {
         const float2 *zb = a.Z + (jj - a.jz0) * NPOL * N + (long long)k2_0 * L;
@@ -518,30 +517,6 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
         const float2 *zb = a.Z + (j - a.jz0) * NPOL * N + (long long)k2_0 * L;
         if constexpr (ZPRE) {
             z_to_lds(zc);
-        } else if constexpr (L >= 1024 && G::PS == 4) {
-            // one complex value per access: consecutive lanes write
-            // consecutive LDS words (with a pad word per 16, the paired form
-            // below halves the accesses but doubles the LDS bank conflicts of
-            // long rows; with a pad per 32 the paired form is conflict-free,
-            // and measured 3 % faster on 2048-point matrix-core rows)
-#pragma unroll
-            for (int s = 0; s < (NPOL * G::TP) / NB; ++s) {
-                const int i = tid + NB * s;
-                const int n1 = i & (L - 1);
-                const int cc = (i >> G::logL) & (G::T - 1);
-                const int pp = i >> (G::logL + G::logT);
-                const float2 *zp = zb + (unsigned)(pp * (int)N + cc * L + n1);
-                const int ad = G::idx(pp, cc, n1);
-                if (a.znt) {
-                    const float *zf = reinterpret_cast<const float *>(zp);
-                    sre[ad] = __builtin_nontemporal_load(zf);
-                    sim[ad] = __builtin_nontemporal_load(zf + 1);
-                } else {
-                    const float2 z = *zp;
-                    sre[ad] = z.x;
-                    sim[ad] = z.y;
-                }
-            }
         } else {
             // two consecutive n1 (16 bytes) per access
 #pragma unroll
