@@ -72,7 +72,13 @@ typedef enum {
 /* PFB: pre-filter then FFT.  DIRECT: FFT of each frame (P must be 1). */
 typedef enum { PFBS_MODE_PFB = 0, PFBS_MODE_DIRECT = 1 } pfbs_mode;
 
-/* Arithmetic of the FFT.  FP32: every stage on the vector ALUs in float.
+/* Arithmetic of the FFT.  FP32: every stage on the vector ALUs in float,
+ * except that from 2^18 channels the row pass of the two-pass FFT (its second
+ * set of sub-transforms, Section 4 "parallel FFTs") runs in double on the
+ * same ALUs: a strong tone's energy sits in one intermediate row and
+ * single-precision rounding of that row, spread over all of its channels,
+ * exceeds 1e-5 of the integrated power there; the intermediate between the
+ * passes, the products' accumulation and the dumps stay FP32.
  * MFMA_FP16: each radix-16 stage as a product with the 16x16 DFT matrix on
  * the FP16 matrix cores (v_mfma_f32_16x16x32_f16, FP32 accumulation), matrix
  * and data rounded to single FP16 values after a per-butterfly power-of-two
@@ -118,8 +124,11 @@ typedef enum { PFBS_OUT_PRODUCTS = 0, PFBS_OUT_STOKES = 1 } pfbs_output;
  *                 position (k + N/2) mod N, negative frequencies first);
  *                 batched plans: 0 only;
  *   stream_z    : 1 = streaming (non-temporal) stores and loads of the
- *                 two-pass intermediate, 0 = ordinary ones.
- * The last five only change speed, never results beyond FP32 rounding order.
+ *                 two-pass intermediate, 0 = ordinary ones;
+ *   tap_unroll  : see the field (speed only; the same arithmetic in the same
+ *                 order either way, so the same bits).
+ * chunk, split_n2, group_bytes, col_run, stream_z and tap_unroll only change
+ * speed, never results beyond FP32 rounding order.
  * With tune = 1 they are taken from the autotune cache when it holds an
  * entry for this device and shape (see pfbs_autotune); with tune = 2 a
  * missing entry is measured first.                                          */
@@ -141,6 +150,9 @@ typedef struct {
     int32_t stream_z;
     int32_t output;     /* pfbs_output */
     int32_t fftshift;   /* 1: channels in shifted order, k' = (k + N/2) mod N */
+    int32_t tap_unroll; /* pre-filter tap loop: 0 automatic, 1 unrolled at compile
+                           time (P = 4 or 8), 2 a loop over P at run time */
+    int32_t pad_;
 } pfbs_plan_desc;
 
 /* Create a plan (FP32 arithmetic; Section 4, initialisation: coefficients are
@@ -199,7 +211,10 @@ pfbs_status pfbs_plan_reset(pfbs_plan *plan);
 /* Test hook: the FP32 pre-filter output y_j[n] of the spectra that the next
  * block would complete, without changing the plan.  d_y: device,
  * float [n_spectra][n_pol][N][2]; *n_spectra (host) receives the count.
- * Same device code as the pre-filter inside pfbs_execute. */
+ * A kernel of its own: it shares the frame addressing (block or tap history)
+ * and the per-tap multiply-add with the kernels of pfbs_execute, in the same
+ * tap order, but not their tile addressing; the production kernels' indexing
+ * is checked through pfbs_execute itself (one-hot taps against direct mode). */
 pfbs_status pfbs_debug_pfb(pfbs_plan *plan, const void *d_block, int64_t n_time_samples,
                            float *d_y, int64_t y_capacity_spectra, int64_t *n_spectra,
                            void *stream);
@@ -217,6 +232,11 @@ typedef struct {
     int64_t spectra_done;           /* valid spectra produced so far           */
     int64_t dumps_done;             /* dumps emitted so far                    */
     int64_t device_bytes;           /* device memory held by the plan          */
+    int32_t row_arith;              /* arithmetic of the row pass of the two-pass
+                                       FFT: 0 FP32, 1 FP16 matrix cores, 2 split
+                                       FP16 matrix cores, 3 FP64 (FP32 plans from
+                                       2^18 channels); -1 for a single-pass FFT */
+    int32_t pad_;
 } pfbs_plan_info;
 
 pfbs_status pfbs_plan_get_info(const pfbs_plan *plan, pfbs_plan_info *info);
@@ -236,7 +256,7 @@ pfbs_status pfbs_plan_timing_kinds(pfbs_plan *plan, uint32_t kinds);
 pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches, int32_t n);
 
 /* Autotuner.  Times candidate settings of the speed-only fields (split_n2,
- * chunk, col_run, stream_z) for the plan shape in *desc on its device, each
+ * chunk, col_run, stream_z, tap_unroll) for the plan shape in *desc on its device, each
  * on the same synthetic stream of device blocks of block_samples time samples
  * (a positive multiple of N; 0 = 2^24; as many distinct blocks as make at
  * least 512 MB, at most 16, so the input streams from HBM and not from the
@@ -246,7 +266,7 @@ pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches
  * *best_samples_per_s (may be NULL).  At most max_candidates settings are
  * timed (0 = all).  If the environment variable PFBS_TUNE_CACHE names a file,
  * the result is appended to it as one text line
- *   pfbs-tune-v2 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z samples_per_s
+ *   pfbs-tune-v3 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z tap_unroll samples_per_s
  * (version: the source digest of pfbs_version, so a rebuilt library with
  * changed kernels does not reuse old measurements)
  * and later plans created with tune != 0 reuse the newest matching line.

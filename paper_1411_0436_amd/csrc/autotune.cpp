@@ -40,16 +40,16 @@ std::string device_arch() {
 struct Line {
     std::string arch, version;
     long long N, n_int, block, split;
-    int P, mode, npol, prec, chunk, col_run, stream_z;
+    int P, mode, npol, prec, chunk, col_run, stream_z, tap_unroll;
     double sps;
 };
 
 bool parse(const char *s, Line &l) {
     char tag[32], arch[64], ver[64];
-    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %lf", tag, arch, ver, &l.N, &l.P,
+    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %lf", tag, arch, ver, &l.N, &l.P,
                    &l.mode, &l.npol, &l.n_int, &l.prec, &l.block, &l.split, &l.chunk, &l.col_run,
-                   &l.stream_z, &l.sps);
-    if (n != 15 || strcmp(tag, "pfbs-tune-v2") != 0) return false;
+                   &l.stream_z, &l.tap_unroll, &l.sps);
+    if (n != 16 || strcmp(tag, "pfbs-tune-v3") != 0) return false;
     l.arch = arch;
     l.version = ver;
     return true;
@@ -87,13 +87,14 @@ void cache_append(const pfbs_plan_desc *d, int64_t block, const pfbs_plan_desc *
     std::lock_guard<std::mutex> lk(g_cache_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "pfbs-tune-v2 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %.6e\n", device_arch().c_str(),
+    fprintf(f, "pfbs-tune-v3 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %.6e\n", device_arch().c_str(),
             PFBS_SOURCE_DIGEST, (long long)d->N, d->P, d->mode, d->n_pol, (long long)d->n_int, d->precision, (long long)block,
-            (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, sps);
+            (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, b->tap_unroll, sps);
     fclose(f);
 }
 
 // Valid column lengths of the two-pass FFT for N (mirrors the plan's checks).
+// Column lengths worth timing: every one the kernels support.
 std::vector<int64_t> splits_for(int64_t N) {
     std::vector<int64_t> v;
     if (N <= pfbs::kMaxSinglePass) {
@@ -150,6 +151,7 @@ pfbs_status tune_lookup(const pfbs_plan_desc *desc, bool measure_if_missing, pfb
         out->chunk = l.chunk;
         out->col_run = l.col_run;
         out->stream_z = l.stream_z;
+        out->tap_unroll = l.tap_unroll;
         return PFBS_OK;
     }
     if (!measure_if_missing) return PFBS_OK;
@@ -179,17 +181,21 @@ extern "C" pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_s
     const bool four = base.N > pfbs::kMaxSinglePass;
     const int chunks[] = {8, 16, 32, 64};
     const int runs[] = {1, 2, 4};
+    // the tap loop's form matters only with the filter at 4 or 8 taps
+    const bool unrollable = base.mode == PFBS_MODE_PFB && (base.P == 4 || base.P == 8);
     for (int64_t sp : splits)
         for (int ch : chunks)
-            for (int r = 0; r < (four ? 3 : 1); ++r) {
-                pfbs_plan_desc c = base;
-                c.split_n2 = sp;
-                c.chunk = ch;
-                c.col_run = four ? runs[r] : 0;
-                c.stream_z = 0;
-                c.group_bytes = 0;
-                cands.push_back(c);
-            }
+            for (int r = 0; r < (four ? 3 : 1); ++r)
+                for (int u = unrollable ? 1 : 0; u <= (unrollable ? 2 : 0); ++u) {
+                    pfbs_plan_desc c = base;
+                    c.split_n2 = sp;
+                    c.chunk = ch;
+                    c.col_run = four ? runs[r] : 0;
+                    c.stream_z = 0;
+                    c.group_bytes = 0;
+                    c.tap_unroll = u;
+                    cands.push_back(c);
+                }
     if (four) {  // streaming intermediate, at the default split
         pfbs_plan_desc c = base;
         c.stream_z = 1;

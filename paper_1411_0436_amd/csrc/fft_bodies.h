@@ -14,7 +14,7 @@ namespace pfbs {
 // LDS FFT; a thread accumulates the products of fixed output bins of one
 // column in registers; at the end of the chunk the T columns are summed in
 // column order and written as the chunk's partial sum.
-template <int NPOL, bool PFB, int L, int PREC = 0>
+template <int NPOL, bool PFB, int L, int PREC = 0, int PT = 0>
 __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
     typedef Geom<L, kTilePoints, 5> G;
     typedef typename Sample<NPOL>::word4 W4;
@@ -49,22 +49,54 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
 #pragma unroll
             for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
         // work item q: four consecutive points 4q .. 4q+3 of the T columns
-        for (int p = 0; p < P; ++p) {
+        if constexpr (PFB && PT > 0) {
+            // compile-time tap count: the loads of tap p+1 go out before the
+            // multiply-adds of tap p, in registers of their own.  Columns past
+            // the chunk read the frames of its last spectrum (valid memory);
+            // their outputs are never accumulated.
+            typedef typename Sample<NPOL>::word W;
+            auto loads = [&](int p, W4 (&w4)[PTS / 4], float4 (&h4)[PTS / 4]) {
 #pragma unroll
-            for (int g = 0; g < PTS / 4; ++g) {
-                const int i = 4 * (tid + NB * g);
-                const int c = i >> G::logL, n = i & (L - 1);
-                const long long jj = j0 + c;
-                if (jj < je) {
-                    const W4 w4 = *reinterpret_cast<const W4 *>(frame_ptr<NPOL>(a.fr, jj + p, L) + n);
-                    if (PFB) {
-                        const float4 h4 = *reinterpret_cast<const float4 *>(a.taps + p * L + n);
+                for (int g = 0; g < PTS / 4; ++g) {
+                    const int i = 4 * (tid + NB * g);
+                    const int c = i >> G::logL, n = i & (L - 1);
+                    const long long jj = min(j0 + c, je - 1);
+                    const W *fb = frame_ptr<NPOL>(a.fr, jj + p, L);
+                    w4[g] = *reinterpret_cast<const W4 *>(fb + n);
+                    h4[g] = *reinterpret_cast<const float4 *>(a.taps + p * L + n);
+                }
+            };
+            W4 wq[PT][PTS / 4];
+            float4 hq[PT][PTS / 4];
+            loads(0, wq[0], hq[0]);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            tap_fma<NPOL>(y[4 * g + e], part4(h4, e), Sample<NPOL>::part(w4, e));
-                    } else {
+            for (int p = 0; p < PT; ++p) {
+                if (p + 1 < PT) loads(p + 1, wq[p + 1], hq[p + 1]);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4, e), y[4 * g + e]);
+                for (int g = 0; g < PTS / 4; ++g)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        tap_fma<NPOL>(y[4 * g + e], part4(hq[p][g], e), Sample<NPOL>::part(wq[p][g], e));
+            }
+        } else {
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int g = 0; g < PTS / 4; ++g) {
+                    const int i = 4 * (tid + NB * g);
+                    const int c = i >> G::logL, n = i & (L - 1);
+                    const long long jj = j0 + c;
+                    if (jj < je) {
+                        const W4 w4 = *reinterpret_cast<const W4 *>(frame_ptr<NPOL>(a.fr, jj + p, L) + n);
+                        if (PFB) {
+                            const float4 h4 = *reinterpret_cast<const float4 *>(a.taps + p * L + n);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                tap_fma<NPOL>(y[4 * g + e], part4(h4, e), Sample<NPOL>::part(w4, e));
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4, e), y[4 * g + e]);
+                        }
                     }
                 }
             }
@@ -188,7 +220,7 @@ __device__ __forceinline__ void cols_tile_item(int ntiles, int bid, int nblk, in
     }
 }
 
-template <int NPOL, bool PFB, int L, int PREC = 0>
+template <int NPOL, bool PFB, int L, int PREC = 0, int PT = 0>
 __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int nblk) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
@@ -224,15 +256,19 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 #pragma unroll
             for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
         // uniform bases, 32-bit unsigned per-lane offsets
+        // buffer loads: uniform frame / tap-row base in a scalar descriptor,
+        // 32-bit per-lane offsets (no 64-bit address per load and tap held in
+        // vector registers)
+        const unsigned rest = (unsigned)(N - n1_0);   // points from the tile's first column to the frame end
         auto tap_loads = [&](int p, W4 (&w4)[PTS / 4], float4 (&h4)[PTS / 4]) {
-            const W *fb = frame_ptr<NPOL>(a.fr, j + p, N) + n1_0;
-            const float *hb = a.taps + (long long)p * N + n1_0;
+            const Rsrc fr = make_rsrc(frame_ptr<NPOL>(a.fr, j + p, N) + n1_0, rest * (unsigned)sizeof(W));
+            const Rsrc hr = make_rsrc(a.taps + (long long)p * N + n1_0, rest * 4u);
 #pragma unroll
             for (int g = 0; g < PTS / 4; ++g) {
                 const int q = tid + NB * g;
                 const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
-                w4[g] = *reinterpret_cast<const W4 *>(fb + n);
-                if (PFB) h4[g] = *reinterpret_cast<const float4 *>(hb + n);
+                w4[g] = buf_load<W4>(fr, n * (unsigned)sizeof(W));
+                if (PFB) h4[g] = buf_load<float4>(hr, n * 4u);
             }
         };
         W4 w4[PTS / 4];
@@ -243,6 +279,29 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
             for (int g = 0; g < PTS / 4; ++g)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) Sample<NPOL>::unpack(Sample<NPOL>::part(w4[g], e), y[4 * g + e]);
+        } else if constexpr (PT > 0) {
+            // compile-time tap count, fully unrolled: tap p+1's loads go out
+            // before tap p's multiply-adds, each tap in registers of its own,
+            // and the scheduler may not move them across (a rolled loop made
+            // the compiler wait for the next tap's loads at the end of every
+            // iteration, to copy them into the loop-carried registers)
+            W4 wq[PT][PTS / 4];
+            float4 hq[PT][PTS / 4];
+#pragma unroll
+            for (int g = 0; g < PTS / 4; ++g) {
+                wq[0][g] = w4[g];
+                hq[0][g] = h4[g];
+            }
+#pragma unroll
+            for (int p = 0; p < PT; ++p) {
+                if (p + 1 < PT) tap_loads(p + 1, wq[p + 1], hq[p + 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int g = 0; g < PTS / 4; ++g)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        tap_fma<NPOL>(y[4 * g + e], part4(hq[p][g], e), Sample<NPOL>::part(wq[p][g], e));
+            }
         } else {
             for (int p = 0; p < P; ++p) {
                 // the next tap's loads go out before this tap's arithmetic, so
@@ -317,7 +376,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 // spectra instead of 2P.  Each half of the workgroup then transforms and
 // stores one spectrum, exactly as front_cols_body does (same arithmetic in
 // the same order, so the same bits).
-template <int NPOL, int L>
+template <int NPOL, int L, int PT = 0>
 __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid, int nblk) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
@@ -355,25 +414,48 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
             for (int s = 0; s < 4 * GRP; ++s)
 #pragma unroll
                 for (int pp = 0; pp < NPOL; ++pp) y[h][s][pp] = make_float2(0.f, 0.f);
+        const unsigned rest = (unsigned)(N - n1_0);
         auto frame_loads = [&](long long f, W4 (&w4)[GRP]) {
-            const W *fb = frame_ptr<NPOL>(a.fr, min(f, f_last), N) + n1_0;
+            const Rsrc fr = make_rsrc(frame_ptr<NPOL>(a.fr, min(f, f_last), N) + n1_0, rest * (unsigned)sizeof(W));
 #pragma unroll
             for (int g = 0; g < GRP; ++g) {
                 const int q = tid + 2 * NB * g;
                 const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
-                w4[g] = *reinterpret_cast<const W4 *>(fb + n);
+                w4[g] = buf_load<W4>(fr, n * (unsigned)sizeof(W));
             }
         };
         auto tap_loads = [&](int p, float4 (&h4)[GRP]) {
-            const float *hb = a.taps + (long long)p * N + n1_0;
+            const Rsrc hr = make_rsrc(a.taps + (long long)p * N + n1_0, rest * 4u);
 #pragma unroll
             for (int g = 0; g < GRP; ++g) {
                 const int q = tid + 2 * NB * g;
                 const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
-                h4[g] = *reinterpret_cast<const float4 *>(hb + n);
+                h4[g] = buf_load<float4>(hr, n * 4u);
             }
         };
         // xa: frame j+p (first spectrum's tap p), xb: frame j+p+1 (second's)
+        if constexpr (PT > 0) {
+            // compile-time tap count, fully unrolled: frame j+p+2 and tap p+1
+            // are loaded before step p's multiply-adds, in registers of their own
+            W4 xf[PT + 1][GRP];
+            float4 hq[PT][GRP];
+            frame_loads(j, xf[0]);
+            frame_loads(j + 1, xf[1]);
+            tap_loads(0, hq[0]);
+#pragma unroll
+            for (int p = 0; p < PT; ++p) {
+                if (p + 2 <= PT) frame_loads(j + p + 2, xf[p + 2]);
+                if (p + 1 < PT) tap_loads(p + 1, hq[p + 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int g = 0; g < GRP; ++g)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        tap_fma<NPOL>(y[0][4 * g + e], part4(hq[p][g], e), Sample<NPOL>::part(xf[p][g], e));
+                        tap_fma<NPOL>(y[1][4 * g + e], part4(hq[p][g], e), Sample<NPOL>::part(xf[p + 1][g], e));
+                    }
+            }
+        } else {
         W4 xa[GRP], xb[GRP];
         float4 h4[GRP];
         frame_loads(j, xa);
@@ -396,6 +478,7 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
                 xb[g] = xn[g];
                 h4[g] = hn[g];
             }
+        }
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -450,17 +533,26 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
 template <int L> struct BackTile { static constexpr int TP = back_tile_points(L); };
 // LDS padding of the row pass (Geom): PS = 5 measured faster except for FP32
 // rows of 512 points and more (N = 2^17: row pass 0.113 -> 0.093 ms with PS = 4).
-template <int L, int PREC> struct BackPad { static constexpr int PS = (PREC == 0 && L >= 512) ? 4 : 5; };
+template <int L, int PREC> struct BackPad {
+    static constexpr int PS = ((PREC == 0 || PREC == 3) && L >= 512) ? 4 : 5;
+};
 
+// PREC 3: the row FFT and the products in FP64 on the vector ALUs (each
+// product rounded once to FP32 before it is accumulated); the intermediate
+// stays FP32.  A strong tone's energy sits in one intermediate row, and an
+// FP32 row FFT spreads its rounding over every channel of that row.
 template <int NPOL, int L, int PREC = 0>
 __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
     typedef Geom<L, BackTile<L>::TP, BackPad<L, PREC>::PS> G;
+    constexpr bool F64 = PREC == 3;
+    typedef std::conditional_t<F64, double, float> T;
+    typedef typename Cplx<T>::type C;
     constexpr int NB = G::TPP * NPOL;
     constexpr int NP = NPOL == 2 ? 4 : 1;
     constexpr int BINS = G::TP / NB;
     extern __shared__ float smem[];
-    float *sre = smem;
-    float *sim = smem + NPOL * G::plane;
+    T *sre = reinterpret_cast<T *>(smem);
+    T *sim = sre + NPOL * G::plane;
     const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
     const int tile = bid % a.ntiles;
     const long long gid = a.ch.gid0 + bid / a.ntiles;
@@ -470,7 +562,7 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
     const int k2_0 = tile * G::T;
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
     MfmaW Wm{};
-    if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
+    if constexpr (FftPrec<PREC>::IN_LDS) Wm = mfma_dft16_operands(lt & 63);
 
     float acc[BINS][NP];
 #pragma unroll
@@ -538,8 +630,9 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
         if constexpr (ZPRE) {
             if (j + 1 < je) z_loads(j + 1, zc);
         }
-        float2 v[16];
-        fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, NPOL == 1);
+        C v[16];
+        if constexpr (F64) fft_plane<G, FftWave<G, PREC>::value, double>(sre, sim, pol, lt, a.g.tw64, v);
+        else fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, NPOL == 1);
         if constexpr (NPOL == 2) {
             if constexpr (!FftPrec<PREC>::IN_LDS) {
 #pragma unroll
@@ -555,13 +648,13 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
                 const int e = tid + NB * i;
                 const int c = e >> G::logL, k = e & (L - 1);
                 const int ax = G::idx(0, c, k), ay = G::idx(1, c, k);
-                prod4(acc[i], make_float2(sre[ax], sim[ax]), make_float2(sre[ay], sim[ay]));
+                prod4(acc[i], Cx<C>::mk(sre[ax], sim[ax]), Cx<C>::mk(sre[ay], sim[ay]));
             }
             __syncthreads();
         } else {
             if constexpr (FftPrec<PREC>::IN_LDS || FftWave<G, PREC>::value) __syncthreads();
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r][0] += v[r].x * v[r].x + v[r].y * v[r].y;
+            for (int r = 0; r < 16; ++r) acc[r][0] += (float)(v[r].x * v[r].x + v[r].y * v[r].y);
         }
     }
     float *dst = a.part + (gid - a.ch.gid_lo) * (long long)NP * N;

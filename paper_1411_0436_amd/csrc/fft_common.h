@@ -3,6 +3,8 @@
 // in LDS, int8 unpacking and the polarisation products.
 #pragma once
 
+#include <type_traits>
+
 #include "pfbs_internal.h"
 
 namespace pfbs {
@@ -43,41 +45,84 @@ __device__ __forceinline__ void globalise(ReduceArgs &a) {
     a.out = as_global(a.out);
 }
 
+// Raw buffer loads: a wave-uniform base and size in a scalar resource
+// descriptor and a 32-bit per-lane byte offset (a frame or a tap row is at
+// most 4 MB), so a load needs one vector register for its address instead of
+// a 64-bit pair, and loads past `bytes` return zero instead of touching
+// memory.  Word 3 of the descriptor: 32-bit data format, as raw loads
+// require on this architecture.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <class T> __device__ __forceinline__ T buf_load(Rsrc r, unsigned off);
+template <> __device__ __forceinline__ uint4 buf_load<uint4>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float4 buf_load<float4>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ uint2 buf_load<uint2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 // --------------------------------------------------------------- complex --
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
-    return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+// Complex values of the FFT passes: float2 (FP32 arithmetic) or double2 (the
+// FP64 row pass).  Cx<C> gives the real type, a constructor and the DFT
+// constants in that precision.
+template <class C> struct Cx;
+template <> struct Cx<float2> {
+    typedef float R;
+    __device__ __forceinline__ static float2 mk(float a, float b) { return make_float2(a, b); }
+    static constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;  // cos, sin(pi/8)
+    static constexpr float h = 0.70710678118654752440f;                                   // cos(pi/4)
+};
+template <> struct Cx<double2> {
+    typedef double R;
+    __device__ __forceinline__ static double2 mk(double a, double b) { return make_double2(a, b); }
+    static constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+    static constexpr double h = 0.70710678118654752440;
+};
+// Element type of an LDS plane -> its complex type.
+template <class T> struct Cplx;
+template <> struct Cplx<float> { typedef float2 type; };
+template <> struct Cplx<double> { typedef double2 type; };
+
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { return Cx<C>::mk(a.x + b.x, a.y + b.y); }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { return Cx<C>::mk(a.x - b.x, a.y - b.y); }
+template <class C> __device__ __forceinline__ C cmul(C a, C w) {
+    return Cx<C>::mk(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
 }
-__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // a * (-i)
+template <class C> __device__ __forceinline__ C mul_mi(C a) { return Cx<C>::mk(a.y, -a.x); }  // a * (-i)
 
 // Forward DFTs (kernel e^{-2 pi i k n / R}), natural order in and out.
-__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
-    float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
-    float2 t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
+template <class C> __device__ __forceinline__ void dft4(C &a0, C &a1, C &a2, C &a3) {
+    C t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    C t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
     a0 = cadd(t0, t2);
     a2 = csub(t0, t2);
     a1 = cadd(t1, t3);
     a3 = csub(t1, t3);
 }
 
-__device__ __forceinline__ void dft2(float2 *v) {
-    float2 a = v[0];
+template <class C> __device__ __forceinline__ void dft2(C *v) {
+    C a = v[0];
     v[0] = cadd(a, v[1]);
     v[1] = csub(a, v[1]);
 }
 
 // 8 = 2 x 4: n = m + 2r, k = q + 4s.
-__device__ __forceinline__ void dft8(float2 *v) {
-    const float h = 0.70710678118654752440f;
-    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+template <class C> __device__ __forceinline__ void dft8(C *v) {
+    typedef typename Cx<C>::R R;
+    const R h = Cx<C>::h;
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
     dft4(e0, e1, e2, e3);
     dft4(o0, o1, o2, o3);
-    o1 = make_float2((o1.x + o1.y) * h, (o1.y - o1.x) * h);   // * W8^1
-    o2 = mul_mi(o2);                                         // * W8^2
-    o3 = make_float2((o3.y - o3.x) * h, -(o3.x + o3.y) * h);  // * W8^3
+    o1 = Cx<C>::mk((o1.x + o1.y) * h, (o1.y - o1.x) * h);   // * W8^1
+    o2 = mul_mi(o2);                                        // * W8^2
+    o3 = Cx<C>::mk((o3.y - o3.x) * h, -(o3.x + o3.y) * h);  // * W8^3
     v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
     v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
     v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
@@ -85,37 +130,38 @@ __device__ __forceinline__ void dft8(float2 *v) {
 }
 
 // 16 = 4 x 4: n = m + 4r, k = q + 4s; inner twiddle W16^(m q).
-__device__ __forceinline__ void dft16(float2 *v) {
-    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
-    const float h = 0.70710678118654752440f;
-    float2 u[16];
+template <class C> __device__ __forceinline__ void dft16(C *v) {
+    typedef typename Cx<C>::R R;
+    const R c1 = Cx<C>::c1, s1 = Cx<C>::s1, h = Cx<C>::h;
+    C u[16];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        float2 a0 = v[m], a1 = v[m + 4], a2 = v[m + 8], a3 = v[m + 12];
+        C a0 = v[m], a1 = v[m + 4], a2 = v[m + 8], a3 = v[m + 12];
         dft4(a0, a1, a2, a3);
         u[m * 4 + 0] = a0; u[m * 4 + 1] = a1; u[m * 4 + 2] = a2; u[m * 4 + 3] = a3;
     }
-    u[5] = cmul(u[5], make_float2(c1, -s1));                                 // W^1
-    u[6] = make_float2((u[6].x + u[6].y) * h, (u[6].y - u[6].x) * h);        // W^2
-    u[7] = cmul(u[7], make_float2(s1, -c1));                                 // W^3
-    u[9] = make_float2((u[9].x + u[9].y) * h, (u[9].y - u[9].x) * h);        // W^2
-    u[10] = mul_mi(u[10]);                                                   // W^4
-    u[11] = make_float2((u[11].y - u[11].x) * h, -(u[11].x + u[11].y) * h);  // W^6
-    u[13] = cmul(u[13], make_float2(s1, -c1));                               // W^3
-    u[14] = make_float2((u[14].y - u[14].x) * h, -(u[14].x + u[14].y) * h);  // W^6
-    u[15] = cmul(u[15], make_float2(-c1, s1));                               // W^9
+    u[5] = cmul(u[5], Cx<C>::mk(c1, -s1));                                 // W^1
+    u[6] = Cx<C>::mk((u[6].x + u[6].y) * h, (u[6].y - u[6].x) * h);        // W^2
+    u[7] = cmul(u[7], Cx<C>::mk(s1, -c1));                                 // W^3
+    u[9] = Cx<C>::mk((u[9].x + u[9].y) * h, (u[9].y - u[9].x) * h);        // W^2
+    u[10] = mul_mi(u[10]);                                                 // W^4
+    u[11] = Cx<C>::mk((u[11].y - u[11].x) * h, -(u[11].x + u[11].y) * h);  // W^6
+    u[13] = cmul(u[13], Cx<C>::mk(s1, -c1));                               // W^3
+    u[14] = Cx<C>::mk((u[14].y - u[14].x) * h, -(u[14].x + u[14].y) * h);  // W^6
+    u[15] = cmul(u[15], Cx<C>::mk(-c1, s1));                               // W^9
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        float2 b0 = u[q], b1 = u[4 + q], b2 = u[8 + q], b3 = u[12 + q];
+        C b0 = u[q], b1 = u[4 + q], b2 = u[8 + q], b3 = u[12 + q];
         dft4(b0, b1, b2, b3);
         v[q] = b0; v[q + 4] = b1; v[q + 8] = b2; v[q + 12] = b3;
     }
 }
 
-template <int R> __device__ __forceinline__ void dftR(float2 *v);
-template <> __device__ __forceinline__ void dftR<2>(float2 *v) { dft2(v); }
-template <> __device__ __forceinline__ void dftR<4>(float2 *v) { dft4(v[0], v[1], v[2], v[3]); }
-template <> __device__ __forceinline__ void dftR<8>(float2 *v) { dft8(v); }
+template <int R, class C> __device__ __forceinline__ void dftR(C *v) {
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+    else dft8(v);
+}
 
 // -------------------------------------------------------------- geometry --
 
@@ -172,8 +218,9 @@ __device__ __forceinline__ void pass_sync() {
 // lt (0..TPP-1) of polarisation pol does 16/R butterflies: with WAVE, those of
 // its own column of the radix-16 passes (bb + s*L/16), else bb + s*TPP
 // counted across the columns.
-template <class G, int R, bool WAVE>
-__device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int lt) {
+template <class G, int R, bool WAVE, class T = float>
+__device__ __forceinline__ void pass_small(T *sre, T *sim, int pol, int lt) {
+    typedef typename Cplx<T>::type C;
     constexpr int PER = 16 / R;
     constexpr int logLR = G::logL - ilog2c(R);
     constexpr int LR = 1 << logLR;
@@ -187,7 +234,7 @@ __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int 
             bb = b & (LR - 1);
         }
     };
-    float2 v[PER][R];
+    C v[PER][R];
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
         int c, bb;
@@ -195,7 +242,7 @@ __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int a = G::idx(pol, c, bb + r * LR);
-            v[s][r] = make_float2(sre[a], sim[a]);
+            v[s][r] = Cx<C>::mk(sre[a], sim[a]);
         }
     }
     pass_sync<WAVE>();
@@ -218,23 +265,24 @@ __device__ __forceinline__ void pass_small(float *sre, float *sim, int pol, int 
 // reads elements bb + r*L/16, applies W_(16 Ns)^(k r) with k = bb mod Ns, and
 // (except in the last pass) writes element (bb-k)*16 + k + r*Ns.  With WAVE
 // the last pass ends without a barrier.
-template <class G, int I, bool WAVE>
-__device__ __forceinline__ void pass16(float *sre, float *sim, int pol, int lt, const float2 *tw,
-                                       float2 (&v)[16]) {
+template <class G, int I, bool WAVE, class T = float>
+__device__ __forceinline__ void pass16(T *sre, T *sim, int pol, int lt, const typename Cplx<T>::type *tw,
+                                       typename Cplx<T>::type (&v)[16]) {
+    typedef typename Cplx<T>::type C;
     constexpr int Ns = G::r0 * (1 << (4 * I));
     constexpr bool LAST = I == G::n16 - 1;
     const int c = lt >> (G::logL - 4), bb = lt & (G::L16 - 1);
     const int k = bb & (Ns - 1);
-    float2 w[16];
+    C w[16];
     if (Ns > 1) {
-        const float2 *t = tw + G::tw_off(I) + k * 15;
+        const C *t = tw + G::tw_off(I) + k * 15;
 #pragma unroll
         for (int r = 1; r < 16; ++r) w[r] = t[r - 1];
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int a = G::idx(pol, c, bb + r * G::L16);
-        v[r] = make_float2(sre[a], sim[a]);
+        v[r] = Cx<C>::mk(sre[a], sim[a]);
     }
     if (!(WAVE && LAST)) pass_sync<WAVE>();
     if (Ns > 1) {
@@ -254,11 +302,11 @@ __device__ __forceinline__ void pass16(float *sre, float *sim, int pol, int lt, 
     }
 }
 
-template <class G, int I, bool WAVE>
-__device__ __forceinline__ void passes16(float *sre, float *sim, int pol, int lt, const float2 *tw,
-                                         float2 (&v)[16]) {
-    pass16<G, I, WAVE>(sre, sim, pol, lt, tw, v);
-    if constexpr (I + 1 < G::n16) passes16<G, I + 1, WAVE>(sre, sim, pol, lt, tw, v);
+template <class G, int I, bool WAVE, class T = float>
+__device__ __forceinline__ void passes16(T *sre, T *sim, int pol, int lt, const typename Cplx<T>::type *tw,
+                                         typename Cplx<T>::type (&v)[16]) {
+    pass16<G, I, WAVE, T>(sre, sim, pol, lt, tw, v);
+    if constexpr (I + 1 < G::n16) passes16<G, I + 1, WAVE, T>(sre, sim, pol, lt, tw, v);
 }
 
 // Whole batched FFT of the columns of one polarisation plane held in LDS.
@@ -268,12 +316,12 @@ __device__ __forceinline__ void passes16(float *sre, float *sim, int pol, int lt
 // with WAVE (G::WAVE_COLS) the passes synchronise within each wave only, and
 // on return other waves may still be reading the plane: a thread may then
 // overwrite only the positions it holds in v until a workgroup barrier.
-template <class G, bool WAVE = false>
-__device__ __forceinline__ void fft_plane(float *sre, float *sim, int pol, int lt, const float2 *tw,
-                                          float2 (&v)[16]) {
+template <class G, bool WAVE = false, class T = float>
+__device__ __forceinline__ void fft_plane(T *sre, T *sim, int pol, int lt, const typename Cplx<T>::type *tw,
+                                          typename Cplx<T>::type (&v)[16]) {
     static_assert(!WAVE || G::WAVE_COLS, "wave-local passes need columns within one wave");
-    if constexpr (G::r0 > 1) pass_small<G, G::r0, WAVE>(sre, sim, pol, lt);
-    passes16<G, 0, WAVE>(sre, sim, pol, lt, tw, v);
+    if constexpr (G::r0 > 1) pass_small<G, G::r0, WAVE, T>(sre, sim, pol, lt);
+    passes16<G, 0, WAVE, T>(sre, sim, pol, lt, tw, v);
 }
 
 // ------------------------------------------------- matrix-core radix 16 --
@@ -430,8 +478,12 @@ __device__ __forceinline__ void fft_plane_mfma(float *sre, float *sim, int pol, 
 // fft_plane), and with IN_LDS the whole transform is also in LDS in natural
 // order (matrix-core passes only).  WAVE: the FP32 passes synchronise per
 // wave where the geometry allows it (see fft_plane).
-template <int PREC> struct FftPrec { static constexpr bool IN_LDS = PREC != 0; };
-template <class G, int PREC> struct FftWave { static constexpr bool value = PREC == 0 && G::WAVE_COLS; };
+// PREC: 0 FP32, 1 FP16 matrix cores, 2 split-FP16 matrix cores, 3 FP64 (row
+// pass only; vector ALUs, fft_plane in double).
+template <int PREC> struct FftPrec { static constexpr bool IN_LDS = PREC == 1 || PREC == 2; };
+template <class G, int PREC> struct FftWave {
+    static constexpr bool value = (PREC == 0 || PREC == 3) && G::WAVE_COLS;
+};
 
 template <class G, int PREC>
 __device__ __forceinline__ void fft_plane_p(float *sre, float *sim, int pol, int lt, const float2 *tw,
@@ -525,6 +577,15 @@ __device__ __forceinline__ void prod4(float (&acc)[4], float2 X, float2 Y) {
     acc[1] += Y.x * Y.x + Y.y * Y.y;
     acc[2] += X.x * Y.x + X.y * Y.y;
     acc[3] += X.y * Y.x - X.x * Y.y;
+}
+
+// The same from double-precision spectra, each product rounded once to FP32
+// before it is accumulated.
+__device__ __forceinline__ void prod4(float (&acc)[4], double2 X, double2 Y) {
+    acc[0] += (float)(X.x * X.x + X.y * X.y);
+    acc[1] += (float)(Y.x * Y.x + Y.y * Y.y);
+    acc[2] += (float)(X.x * Y.x + X.y * Y.y);
+    acc[3] += (float)(X.y * Y.x - X.x * Y.y);
 }
 
 }  // namespace pfbs

@@ -235,8 +235,10 @@ __global__ void k_taps(float *h, long long N, int P, int window, const double *c
 }
 
 // Radix-16 pass twiddles W_(16 Ns)^(k r), k < Ns, r = 1..15, for the passes
-// Ns = r0 * 16^i (i < n16), concatenated.  FP64 sincospi, then FP32.
-__global__ void k_tw16(float2 *tw, int r0, int n16) {
+// Ns = r0 * 16^i (i < n16), concatenated.  FP64 sincospi, then rounded to
+// the table's type (float2, or kept in FP64 for the FP64 row pass).
+template <class C>
+__global__ void k_tw16(C *tw, int r0, int n16) {
     long long off = 0;
     long long Ns = r0;
     for (int i = 0; i < n16; ++i) {
@@ -248,7 +250,8 @@ __global__ void k_tw16(float2 *tw, int r0, int n16) {
             const long long kr = (k * r) % M;
             double s, c;
             sincospi(-2.0 * (double)kr / (double)M, &s, &c);
-            tw[off + e] = make_float2((float)c, (float)s);
+            if constexpr (sizeof(C) == sizeof(float2)) tw[off + e] = make_float2((float)c, (float)s);
+            else tw[off + e] = make_double2(c, s);
         }
         off += cnt;
         Ns *= 16;
@@ -310,7 +313,13 @@ hipError_t launch_tables_taps(float *h, long long N, int P, int window, const do
 
 hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s) {
     const int logL = ilog2c(L);
-    hipLaunchKernelGGL(k_tw16, dim3(64), dim3(256), 0, s, tw, 1 << (logL % 4), logL / 4);
+    hipLaunchKernelGGL(k_tw16<float2>, dim3(64), dim3(256), 0, s, tw, 1 << (logL % 4), logL / 4);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_tw16_f64(double2 *tw, int L, hipStream_t s) {
+    const int logL = ilog2c(L);
+    hipLaunchKernelGGL(k_tw16<double2>, dim3(64), dim3(256), 0, s, tw, 1 << (logL % 4), logL / 4);
     return hipGetLastError();
 }
 
@@ -323,7 +332,10 @@ size_t front_lds_bytes(const Geo &g, int npol) {
     const size_t Lp = (size_t)lds_pitch(g.L);
     return (size_t)2 * npol * g.T * Lp * sizeof(float);
 }
-size_t back_lds_bytes(const Geo &g, int npol) { return front_lds_bytes(g, npol); }
+// The FP64 row pass (prec 3) keeps double planes.
+size_t back_lds_bytes(const Geo &g, int npol, int prec) {
+    return front_lds_bytes(g, npol) * (prec == 3 ? 2 : 1);
+}
 
 hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int prec, int n_items,
                         hipStream_t s) {

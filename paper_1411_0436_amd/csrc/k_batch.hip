@@ -17,7 +17,7 @@ __device__ __forceinline__ int find_entry(const E *t, int n, int bid) {
     return e;
 }
 
-template <int NPOL, bool PFB, int L>
+template <int NPOL, bool PFB, int L, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_multi_single(const BatchFrontEntry *__restrict__ t, int n) {
     if (n <= 0) return;
     const int e = find_entry(t, n, blockIdx.x);
@@ -27,10 +27,10 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_multi_single(const 
     // stay in registers instead of being reloaded after every store
     FrontArgs a = t[e].a;
     globalise(a);
-    front_single_body<NPOL, PFB, L>(a, vb);
+    front_single_body<NPOL, PFB, L, 0, PT>(a, vb);
 }
 
-template <int NPOL, bool PFB, int L>
+template <int NPOL, bool PFB, int L, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_multi_cols(const BatchFrontEntry *__restrict__ t, int n) {
     if (n <= 0) return;
     const int e = find_entry(t, n, blockIdx.x);
@@ -38,10 +38,10 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_multi_cols(const Ba
     if (vb < 0 || vb >= wgn) return;
     FrontArgs a = t[e].a;
     globalise(a);
-    front_cols_body<NPOL, PFB, L>(a, vb, wgn);
+    front_cols_body<NPOL, PFB, L, 0, PT>(a, vb, wgn);
 }
 
-template <int NPOL, int L>
+template <int NPOL, int L, int PREC = 0>
 __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_multi_back(const BatchBackEntry *__restrict__ t, int n) {
     if (n <= 0) return;
     const int e = find_entry(t, n, blockIdx.x);
@@ -49,20 +49,27 @@ __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_multi_back(cons
     if (vb < 0 || vb >= t[e].wgn) return;
     BackArgs a = t[e].a;
     globalise(a);
-    back_body<NPOL, L>(a, vb);
+    back_body<NPOL, L, PREC>(a, vb);
 }
 
 #define PFBS_M_SINGLE(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 #define PFBS_M_COLS(X) X(64) X(128) X(256) X(512)
 #define PFBS_M_BACK(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
-const void *multi_front_fn(int npol, int kind, int pfb, int L) {
+// pt: compile-time tap count of the variant (4 or 8), 0 = from the entry.
+const void *multi_front_fn(int npol, int kind, int pfb, int L, int pt) {
 #define PFBS_F(KERN, LL)                                                                       \
     if (L == LL) {                                                                             \
-        if (npol == 2) return pfb ? reinterpret_cast<const void *>(&KERN<2, true, LL>)         \
-                                  : reinterpret_cast<const void *>(&KERN<2, false, LL>);       \
-        return pfb ? reinterpret_cast<const void *>(&KERN<1, true, LL>)                        \
-                   : reinterpret_cast<const void *>(&KERN<1, false, LL>);                      \
+        if (npol == 2) {                                                                       \
+            if (!pfb) return reinterpret_cast<const void *>(&KERN<2, false, LL>);              \
+            if (pt == 4) return reinterpret_cast<const void *>(&KERN<2, true, LL, 4>);         \
+            if (pt == 8) return reinterpret_cast<const void *>(&KERN<2, true, LL, 8>);         \
+            return reinterpret_cast<const void *>(&KERN<2, true, LL>);                         \
+        }                                                                                      \
+        if (!pfb) return reinterpret_cast<const void *>(&KERN<1, false, LL>);                  \
+        if (pt == 4) return reinterpret_cast<const void *>(&KERN<1, true, LL, 4>);             \
+        if (pt == 8) return reinterpret_cast<const void *>(&KERN<1, true, LL, 8>);             \
+        return reinterpret_cast<const void *>(&KERN<1, true, LL>);                             \
     }
     if (kind == 0) {
 #define PFBS_S(LL) PFBS_F(k_multi_single, LL)
@@ -77,10 +84,15 @@ const void *multi_front_fn(int npol, int kind, int pfb, int L) {
     return nullptr;
 }
 
-const void *multi_back_fn(int npol, int L) {
-#define PFBS_B(LL)                                                                             \
-    if (L == LL) return npol == 2 ? reinterpret_cast<const void *>(&k_multi_back<2, LL>)       \
-                                  : reinterpret_cast<const void *>(&k_multi_back<1, LL>);
+// prec: 0 FP32, 3 FP64 row pass.
+const void *multi_back_fn(int npol, int L, int prec) {
+#define PFBS_B(LL)                                                                                   \
+    if (L == LL) {                                                                                   \
+        if (prec == 3) return npol == 2 ? reinterpret_cast<const void *>(&k_multi_back<2, LL, 3>)    \
+                                        : reinterpret_cast<const void *>(&k_multi_back<1, LL, 3>);   \
+        if (prec == 0) return npol == 2 ? reinterpret_cast<const void *>(&k_multi_back<2, LL>)       \
+                                        : reinterpret_cast<const void *>(&k_multi_back<1, LL>);      \
+    }
     PFBS_M_BACK(PFBS_B)
 #undef PFBS_B
     return nullptr;
@@ -91,19 +103,21 @@ hipError_t init_batch(int lds_limit) {
     for (int npol = 1; npol <= 2; ++npol)
         for (int pfb = 0; pfb <= 1; ++pfb)
             for (int kind = 0; kind <= 1; ++kind)
-                for (int L = 16; L <= 4096; L *= 2) {
-                    const void *f = multi_front_fn(npol, kind, pfb, L);
-                    if (!f) continue;
-                    hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
-                    if (r != hipSuccess) e = r;
-                }
+                for (int L = 16; L <= 4096; L *= 2)
+                    for (int pt : {0, 4, 8}) {
+                        const void *f = multi_front_fn(npol, kind, pfb, L, pt);
+                        if (!f) continue;
+                        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
+                        if (r != hipSuccess) e = r;
+                    }
     for (int npol = 1; npol <= 2; ++npol)
-        for (int L = 32; L <= 4096; L *= 2) {
-            const void *f = multi_back_fn(npol, L);
-            if (!f) continue;
-            hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
-            if (r != hipSuccess) e = r;
-        }
+        for (int L = 32; L <= 4096; L *= 2)
+            for (int prec : {0, 3}) {
+                const void *f = multi_back_fn(npol, L, prec);
+                if (!f) continue;
+                hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
+                if (r != hipSuccess) e = r;
+            }
     return e;
 }
 

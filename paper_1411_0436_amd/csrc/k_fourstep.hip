@@ -12,17 +12,19 @@ namespace pfbs {
 // and costs where it forces large spills.
 template <int L, int PREC> struct ColsMinWaves {
     static constexpr int value =
-        (PREC == 0 && L == 512) || (PREC == 1 && L == 128) || (PREC == 2 && (L == 128 || L == 256)) ? 4 : 1;
+        PREC == 0 || (PREC == 1 && L == 128) || (PREC == 2 && (L == 128 || L == 256)) ? 4 : 1;
 };
 
-template <int NPOL, bool PFB, int L, int PREC>
+// PT: the pre-filter's tap count as a compile-time constant (its loop fully
+// unrolled and software-pipelined), 0 = taken from the arguments.
+template <int NPOL, bool PFB, int L, int PREC, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL, (ColsMinWaves<L, PREC>::value)) void k_front_cols(FrontArgs a) {
-    front_cols_body<NPOL, PFB, L, PREC>(a, blockIdx.x, gridDim.x);
+    front_cols_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x, gridDim.x);
 }
 
-template <int NPOL, int L>
+template <int NPOL, int L, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL * 2) void k_front_cols_pair(FrontArgs a) {
-    front_cols_pair_body<NPOL, L>(a, blockIdx.x, gridDim.x);
+    front_cols_pair_body<NPOL, L, PT>(a, blockIdx.x, gridDim.x);
 }
 
 template <int NPOL, int L, int PREC>
@@ -38,18 +40,24 @@ template <int PREC>
 hipError_t launch_cols_p(const FrontArgs &a, int npol, bool pfb, dim3 grid, dim3 block, size_t lds,
                          hipStream_t s) {
     switch (a.g.L) {
+#define PFBS_PFB(NP, LL)                                                                            \
+    switch (pfb ? (a.pt ? a.pt : -1) : 0) {                                                                        \
+    case 0: PFBS_LAUNCH((k_front_cols<NP, false, LL, PREC>), grid, block, lds, s, a); break;        \
+    case 4: PFBS_LAUNCH((k_front_cols<NP, true, LL, PREC, 4>), grid, block, lds, s, a); break;      \
+    case 8: PFBS_LAUNCH((k_front_cols<NP, true, LL, PREC, 8>), grid, block, lds, s, a); break;      \
+    default: PFBS_LAUNCH((k_front_cols<NP, true, LL, PREC>), grid, block, lds, s, a); break;        \
+    }
 #define PFBS_CASE(LL)                                                                               \
     case LL:                                                                                        \
         if (npol == 2) {                                                                            \
-            if (pfb) PFBS_LAUNCH((k_front_cols<2, true, LL, PREC>), grid, block, lds, s, a); \
-            else PFBS_LAUNCH((k_front_cols<2, false, LL, PREC>), grid, block, lds, s, a);    \
+            PFBS_PFB(2, LL)                                                                         \
         } else {                                                                                    \
-            if (pfb) PFBS_LAUNCH((k_front_cols<1, true, LL, PREC>), grid, block, lds, s, a); \
-            else PFBS_LAUNCH((k_front_cols<1, false, LL, PREC>), grid, block, lds, s, a);    \
+            PFBS_PFB(1, LL)                                                                         \
         }                                                                                           \
         break;
         PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
+#undef PFBS_PFB
     default:
         return hipErrorInvalidValue;
     }
@@ -83,8 +91,12 @@ hipError_t init_fourstep_p(int lds_limit) {
     } while (0);
 #define PFBS_CASE(LL)                              \
     PFBS_ATTR((k_front_cols<2, true, LL, PREC>))   \
+    PFBS_ATTR((k_front_cols<2, true, LL, PREC, 4>)) \
+    PFBS_ATTR((k_front_cols<2, true, LL, PREC, 8>)) \
     PFBS_ATTR((k_front_cols<2, false, LL, PREC>))  \
     PFBS_ATTR((k_front_cols<1, true, LL, PREC>))   \
+    PFBS_ATTR((k_front_cols<1, true, LL, PREC, 4>)) \
+    PFBS_ATTR((k_front_cols<1, true, LL, PREC, 8>)) \
     PFBS_ATTR((k_front_cols<1, false, LL, PREC>))
     PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
@@ -92,6 +104,20 @@ hipError_t init_fourstep_p(int lds_limit) {
     PFBS_BACK_CASES(PFBS_CASE)
 #undef PFBS_CASE
 #undef PFBS_ATTR
+    return e;
+}
+// Row kernels only (the FP64 row pass has no column kernels of its own).
+template <int PREC>
+hipError_t init_back_p(int lds_limit) {
+    hipError_t e = hipSuccess;
+#define PFBS_CASE(LL)                                                                                       \
+    for (const void *fn : {reinterpret_cast<const void *>(k_back<2, LL, PREC>),                                \
+                           reinterpret_cast<const void *>(k_back<1, LL, PREC>)}) {                             \
+        hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);       \
+        if (r != hipSuccess) e = r;                                                                         \
+    }
+    PFBS_BACK_CASES(PFBS_CASE)
+#undef PFBS_CASE
     return e;
 }
 }  // namespace
@@ -103,13 +129,23 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, i
         if (prec != 0 || !pfb) return hipErrorInvalidValue;
         const dim3 block2(2 * block.x);
         switch (a.g.L) {
+#define PFBS_PAIR(NP, LL)                                                                            \
+    switch (a.pt) {                                                                                  \
+    case 4: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 4>), grid, block2, 2 * lds, s, a); break;         \
+    case 8: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 8>), grid, block2, 2 * lds, s, a); break;         \
+    default: PFBS_LAUNCH((k_front_cols_pair<NP, LL>), grid, block2, 2 * lds, s, a); break;           \
+    }
 #define PFBS_CASE(LL)                                                                                \
     case LL:                                                                                         \
-        if (npol == 2) PFBS_LAUNCH((k_front_cols_pair<2, LL>), grid, block2, 2 * lds, s, a); \
-        else PFBS_LAUNCH((k_front_cols_pair<1, LL>), grid, block2, 2 * lds, s, a);           \
+        if (npol == 2) {                                                                             \
+            PFBS_PAIR(2, LL)                                                                         \
+        } else {                                                                                     \
+            PFBS_PAIR(1, LL)                                                                         \
+        }                                                                                            \
         break;
             PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
+#undef PFBS_PAIR
         default:
             return hipErrorInvalidValue;
         }
@@ -124,27 +160,32 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, i
 }
 
 hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s) {
-    const size_t lds = back_lds_bytes(a.g, npol);
+    const size_t lds = back_lds_bytes(a.g, npol, prec);
     const dim3 grid(n_chunks * a.ntiles), block(a.g.T * a.g.L / 16 * npol);
     switch (prec) {
     case 0: return launch_back_p<0>(a, npol, grid, block, lds, s);
     case 1: return launch_back_p<1>(a, npol, grid, block, lds, s);
     case 2: return launch_back_p<2>(a, npol, grid, block, lds, s);
+    case 3: return a.g.tw64 ? launch_back_p<3>(a, npol, grid, block, lds, s) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t init_fourstep(int lds_limit) {
     hipError_t e0 = init_fourstep_p<0>(lds_limit), e1 = init_fourstep_p<1>(lds_limit),
-               e2 = init_fourstep_p<2>(lds_limit);
-    return e0 != hipSuccess ? e0 : (e1 != hipSuccess ? e1 : e2);
+               e2 = init_fourstep_p<2>(lds_limit), e3 = init_back_p<3>(lds_limit);
+    return e0 != hipSuccess ? e0 : (e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3));
 }
 
 bool init_fourstep_pair(int lds_limit) {
     bool ok = true;
 #define PFBS_CASE(LL)                                                                                           \
     for (const void *fn : {reinterpret_cast<const void *>(k_front_cols_pair<2, LL>),                              \
-                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL>)})                             \
+                           reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 4>),                           \
+                           reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 8>),                           \
+                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL>),                              \
+                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 4>),                           \
+                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 8>)})                          \
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess) ok = false;
     PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE

@@ -4,9 +4,11 @@
 
 namespace pfbs {
 
-template <int NPOL, bool PFB, int L, int PREC>
+// PT: the pre-filter's tap count as a compile-time constant (its loop fully
+// unrolled and software-pipelined), 0 = taken from the arguments.
+template <int NPOL, bool PFB, int L, int PREC, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_single(FrontArgs a) {
-    front_single_body<NPOL, PFB, L, PREC>(a, blockIdx.x);
+    front_single_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x);
 }
 
 #define PFBS_SINGLE_CASES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
@@ -16,18 +18,24 @@ template <int PREC>
 hipError_t launch_single_p(const FrontArgs &a, int npol, bool pfb, dim3 grid, dim3 block, size_t lds,
                            hipStream_t s) {
     switch (a.g.L) {
+#define PFBS_PFB(NP, LL)                                                                              \
+    switch (pfb ? (a.pt ? a.pt : -1) : 0) {                                                                          \
+    case 0: PFBS_LAUNCH((k_front_single<NP, false, LL, PREC>), grid, block, lds, s, a); break;        \
+    case 4: PFBS_LAUNCH((k_front_single<NP, true, LL, PREC, 4>), grid, block, lds, s, a); break;      \
+    case 8: PFBS_LAUNCH((k_front_single<NP, true, LL, PREC, 8>), grid, block, lds, s, a); break;      \
+    default: PFBS_LAUNCH((k_front_single<NP, true, LL, PREC>), grid, block, lds, s, a); break;        \
+    }
 #define PFBS_CASE(LL)                                                                                 \
     case LL:                                                                                          \
         if (npol == 2) {                                                                              \
-            if (pfb) PFBS_LAUNCH((k_front_single<2, true, LL, PREC>), grid, block, lds, s, a); \
-            else PFBS_LAUNCH((k_front_single<2, false, LL, PREC>), grid, block, lds, s, a);    \
+            PFBS_PFB(2, LL)                                                                           \
         } else {                                                                                      \
-            if (pfb) PFBS_LAUNCH((k_front_single<1, true, LL, PREC>), grid, block, lds, s, a); \
-            else PFBS_LAUNCH((k_front_single<1, false, LL, PREC>), grid, block, lds, s, a);    \
+            PFBS_PFB(1, LL)                                                                           \
         }                                                                                             \
         break;
         PFBS_SINGLE_CASES(PFBS_CASE)
 #undef PFBS_CASE
+#undef PFBS_PFB
     default:
         return hipErrorInvalidValue;
     }
@@ -45,8 +53,12 @@ hipError_t init_single_p(int lds_limit) {
     } while (0);
 #define PFBS_CASE(LL)                                \
     PFBS_ATTR((k_front_single<2, true, LL, PREC>))   \
+    PFBS_ATTR((k_front_single<2, true, LL, PREC, 4>)) \
+    PFBS_ATTR((k_front_single<2, true, LL, PREC, 8>)) \
     PFBS_ATTR((k_front_single<2, false, LL, PREC>))  \
     PFBS_ATTR((k_front_single<1, true, LL, PREC>))   \
+    PFBS_ATTR((k_front_single<1, true, LL, PREC, 4>)) \
+    PFBS_ATTR((k_front_single<1, true, LL, PREC, 8>)) \
     PFBS_ATTR((k_front_single<1, false, LL, PREC>))
     PFBS_SINGLE_CASES(PFBS_CASE)
 #undef PFBS_CASE

@@ -15,6 +15,16 @@ constexpr int kMaxSinglePass = 4096; // largest N done by one kernel (T = 1)
 // least 1024 (whole waves per polarisation; 2048 measured slower).
 constexpr int back_tile_points(long long n1) { return n1 < 1024 ? 1024 : (int)n1; }
 
+// Arithmetic of the row pass of the two-pass FFT for an FP32 plan: from 2^18
+// channels it runs in FP64 on the vector ALUs (internal precision code 3;
+// these ALUs issue FP64 at their unpacked FP32 rate).  A strong tone's energy
+// sits in one intermediate row, and an FP32 row FFT spreads the rounding of
+// that row over all of its channels: on the largest mode (N = 2^19, 64
+// spectra per dump) FP32 rows miss 1e-5 per channel in some dumps (1.2e-5),
+// with 16 spectra per dump by more (1.7e-5).
+constexpr int kRowF64 = 3;
+constexpr int fp32_row_precision(long long N) { return N >= (1LL << 18) ? kRowF64 : 0; }
+
 // LDS words allocated per column of an L-point sub-FFT plane: one pad word
 // per 16 elements and one more per column (the larger of the two layouts the
 // kernels use; pads of 0, 3 and 9 words per column measured no better).
@@ -26,6 +36,7 @@ struct Geo {
     int L;
     int T;                // sequences per workgroup step (tile points / L)
     const float2 *tw;     // radix-16 pass twiddles, passes concatenated
+    const double2 *tw64;  // the same in FP64 (row pass in FP64 only, else null)
 };
 
 // Spectrum-chunk enumeration.  Dump d covers global spectra
@@ -62,6 +73,7 @@ struct FrontArgs {
     int ga;
     int znt;                  // 1: streaming (non-temporal) stores of Z
     int pair;                 // 1: two spectra per workgroup step (runs of 2*ga)
+    int pt;                   // compile-time tap count of the kernel (4 or 8), 0 = loop over P
     float2 *Z;                // [spectra of launch][pol][N2][N1]
     long long jz0;            // spectrum index of Z[0]
     const float2 *tw4;        // [n1][k2] = W_N^(n1*k2), N entries
@@ -124,8 +136,11 @@ struct BatchTailEntry {
 };
 
 // Kernels of the batched launches (see k_batch.hip): one per variant.
-const void *multi_front_fn(int npol, int kind, int pfb, int L);
-const void *multi_back_fn(int npol, int L);
+const void *multi_front_fn(int npol, int kind, int pfb, int L, int pt);
+// Compile-time tap count of the pre-filter kernels for P taps (0: taken from
+// the arguments at run time; also 0 without the filter or when not unrolled).
+constexpr int tap_variant(bool pfb, int P, bool unroll) { return unroll && pfb && (P == 4 || P == 8) ? P : 0; }
+const void *multi_back_fn(int npol, int L, int prec);
 const void *batch_tail_fn();
 
 }  // namespace pfbs
@@ -165,6 +180,7 @@ hipError_t launch_synth(uint32_t *words, long long n_words, uint32_t seed, hipSt
 hipError_t launch_tables_taps(float *h, long long N, int P, int window, const double *d_custom,
                               hipStream_t s);
 hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s);
+hipError_t launch_tables_tw16_f64(double2 *tw, int L, hipStream_t s);
 hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_t s);
 // prec: 0 = FP32, 1 = matrix cores with an FP16 DFT matrix, 2 = hi + lo matrix
 hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int prec, int n_items,
@@ -182,6 +198,6 @@ hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long 
 hipError_t kernels_init();   // raise LDS limits once per process/device
 bool init_fourstep_pair(int lds_limit);  // LDS limit of the two-spectra column kernels; false if refused
 size_t front_lds_bytes(const Geo &g, int npol);
-size_t back_lds_bytes(const Geo &g, int npol);
+size_t back_lds_bytes(const Geo &g, int npol, int prec);
 
 }  // namespace pfbs

@@ -112,10 +112,12 @@ struct pfbs_plan {
     int ga_force;        // column-pass spectra per workgroup (0 = automatic)
     int out_stokes, out_shift;  // dump form: Stokes parameters, shifted channel order
     int znt;             // streaming stores/loads of the four-step intermediate
+    int tap_unroll;      // pre-filter tap loop: 1 unrolled at compile time, 2 run-time loop
     bool pair;           // FP32 pre-filter column pass on two spectra per workgroup step
     // device state
     float *taps;
     float2 *twA, *twB, *tw4;
+    double2 *twB64;      // row-pass twiddles in FP64 (FP64 row pass only)
     uint8_t *hist[2];
     int hcur;
     int64_t frame_bytes;
@@ -142,8 +144,8 @@ struct pfbs_batch {
     std::vector<pfbs_plan *> plans;
     int npol;
     // kernel variants present (fixed by the sub-band shapes): one launch each
-    struct FVar { int kind, pfb, L; std::vector<int> plans; };
-    struct BVar { int fvar, L; std::vector<int> plans; };   // row passes of one column-pass group
+    struct FVar { int kind, pfb, L, pt; std::vector<int> plans; };
+    struct BVar { int fvar, L, prec; std::vector<int> plans; };   // row passes of one column-pass group
     std::vector<FVar> fvars;
     std::vector<BVar> bvars;
     // entry tables: device copy read by the kernels, two pinned staging copies
@@ -226,6 +228,7 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
         return fail(PFBS_ERR_INVALID, "Stokes output needs two polarisations");
     if (d->fftshift != 0 && d->fftshift != 1) return fail(PFBS_ERR_INVALID, "fftshift must be 0 or 1");
     if (d->tune < 0 || d->tune > 2) return fail(PFBS_ERR_INVALID, "tune must be 0, 1 or 2");
+    if (d->tap_unroll < 0 || d->tap_unroll > 2) return fail(PFBS_ERR_INVALID, "tap_unroll must be 0, 1 or 2");
     return PFBS_OK;
 }
 
@@ -263,7 +266,7 @@ hipError_t dalloc(pfbs_plan *p, T **ptr, size_t count) {
 }
 
 void free_plan_memory(pfbs_plan *p) {
-    void *bufs[] = {p->taps, p->twA, p->twB, p->tw4, p->hist[0], p->hist[1],
+    void *bufs[] = {p->taps, p->twA, p->twB, p->twB64, p->tw4, p->hist[0], p->hist[1],
                     p->Z, p->part, p->carried[0], p->carried[1]};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -371,19 +374,15 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->precision = desc->precision;
     p->prec_front = desc->precision == PFBS_PREC_MIXED ? PFBS_PREC_FP32 : desc->precision;
     p->prec_back = desc->precision == PFBS_PREC_MIXED ? PFBS_PREC_MFMA_FP16X2 : desc->precision;
+    if (p->prec_back == PFBS_PREC_FP32) p->prec_back = fp32_row_precision(desc->N);
     p->device = dev;
     p->n_int = desc->n_int;
     p->nprod = p->npol == 2 ? 4 : 1;
     p->fourstep = p->N > kMaxSinglePass;
     if (p->fourstep) {
         // Column length (measured fastest): 128 up to 2^15 channels (whole
-        // 128-byte int8 rows per column tile), 256 above.  From 2^18 channels
-        // an FP32 row pass is given the shorter rows of 512 (the smaller
-        // worst-channel rounding error next to strong tones); a matrix-core
-        // row pass (MIXED) is accurate enough with 256.
-        const bool long_rows_ok = p->prec_back != PFBS_PREC_FP32;
-        int64_t n2 = p->N <= (int64_t(1) << 15) ? 128 : 256;
-        if (p->N >= (int64_t(1) << 18) && !long_rows_ok) n2 = 512;
+        // 128-byte int8 rows per column tile), 256 above.
+        const int64_t n2 = p->N <= (int64_t(1) << 15) ? 128 : 256;
         p->N2 = desc->split_n2 ? desc->split_n2 : n2;
         p->N1 = p->N / p->N2;
         p->gA = make_geo((int)p->N2);
@@ -406,6 +405,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->frame_bytes = p->N * 2 * p->npol;
     p->ga_force = desc->col_run;
     p->znt = desc->stream_z;
+    p->tap_unroll = desc->tap_unroll;
     // Two spectra per column-pass step share each tap-row load: measured
     // faster only where the tap table (P*N floats) overflows the 4 MB L2 of
     // an XCD (N = 2^19: column pass -8%; N <= 2^16: +3 to +6%), and with
@@ -413,6 +413,8 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->pair = p->fourstep && p->pfb && p->prec_front == PFBS_PREC_FP32 && g_pair_ok[dev] &&
               p->gA.L <= 256 && (int64_t)p->P * p->N >= (int64_t(1) << 21) &&
               2 * front_lds_bytes(p->gA, p->npol) <= (size_t)kPairLds;
+    // tap loop: unrolled where measured faster (the two-spectra column kernel)
+    if (p->tap_unroll == 0) p->tap_unroll = p->pair ? 1 : 2;
     p->out_stokes = desc->output == PFBS_OUT_STOKES;
     p->out_shift = desc->fftshift;
 
@@ -427,6 +429,10 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
         if (p->fourstep) {
             if ((e = dalloc(p, &p->twB, (size_t)tw16_count(p->gB))) != hipSuccess) break;
             p->gB.tw = p->twB;
+            if (p->prec_back == kRowF64) {
+                if ((e = dalloc(p, &p->twB64, (size_t)tw16_count(p->gB))) != hipSuccess) break;
+                p->gB.tw64 = p->twB64;
+            }
             if ((e = dalloc(p, &p->tw4, (size_t)p->N)) != hipSuccess) break;
         }
         const size_t hbytes = (size_t)(p->P - 1) * p->frame_bytes;
@@ -447,6 +453,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
         if ((e = launch_tables_tw16(p->twA, p->gA.L, s)) != hipSuccess) break;
         if (p->fourstep) {
             if ((e = launch_tables_tw16(p->twB, p->gB.L, s)) != hipSuccess) break;
+            if (p->twB64 && (e = launch_tables_tw16_f64(p->twB64, p->gB.L, s)) != hipSuccess) break;
             if ((e = launch_tables_tw4(p->tw4, p->N1, p->N2, s)) != hipSuccess) break;
         }
         if ((e = hipDeviceSynchronize()) != hipSuccess) break;
@@ -515,6 +522,7 @@ pfbs_status pfbs_plan_get_info(const pfbs_plan *p, pfbs_plan_info *info) {
     info->spectra_done = p->spectra_done;
     info->dumps_done = p->dumps_done;
     info->device_bytes = p->device_bytes;
+    info->row_arith = p->fourstep ? p->prec_back : -1;
     return PFBS_OK;
 }
 
@@ -612,6 +620,7 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
     fa.Z = p->Z;
     fa.tw4 = p->tw4;
     fa.part = p->part;
+    fa.pt = tap_variant(p->pfb, p->P, p->tap_unroll == 1);
     if (!p->fourstep) {
         w.single = fa;
         w.single_chunks = (int)n_chunks;
@@ -915,19 +924,17 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
         }
         b->plans.push_back(p);
         const int kind = p->fourstep ? 1 : 0, pfb = p->pfb ? 1 : 0, L = (int)p->gA.L;
-        auto fv = std::find_if(b->fvars.begin(), b->fvars.end(), [&](const pfbs_batch::FVar &v) {
-            return v.kind == kind && v.pfb == pfb && v.L == L;
-        });
-        if (fv == b->fvars.end()) b->fvars.push_back({kind, pfb, L, {i}});
+        const int pt = tap_variant(p->pfb, p->P, p->tap_unroll == 1);
+        auto same = [&](const pfbs_batch::FVar &v) { return v.kind == kind && v.pfb == pfb && v.L == L && v.pt == pt; };
+        auto fv = std::find_if(b->fvars.begin(), b->fvars.end(), same);
+        if (fv == b->fvars.end()) b->fvars.push_back({kind, pfb, L, pt, {i}});
         else fv->plans.push_back(i);
         if (p->fourstep) {
-            const int fi = (int)(std::find_if(b->fvars.begin(), b->fvars.end(), [&](const pfbs_batch::FVar &v) {
-                                     return v.kind == kind && v.pfb == pfb && v.L == L;
-                                 }) - b->fvars.begin());
+            const int fi = (int)(std::find_if(b->fvars.begin(), b->fvars.end(), same) - b->fvars.begin());
             auto bv = std::find_if(b->bvars.begin(), b->bvars.end(), [&](const pfbs_batch::BVar &v) {
-                return v.fvar == fi && v.L == (int)p->N1;
+                return v.fvar == fi && v.L == (int)p->N1 && v.prec == p->prec_back;
             });
-            if (bv == b->bvars.end()) b->bvars.push_back({fi, (int)p->N1, {i}});
+            if (bv == b->bvars.end()) b->bvars.push_back({fi, (int)p->N1, p->prec_back, {i}});
             else bv->plans.push_back(i);
         }
     }
@@ -1020,7 +1027,7 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             wg_max += (int)((v.kind == 0 ? max_chunks(p, F) : p->ntilesA * (((F + ga - 1) / ga + 7) / 8 * 8)) + 7) & ~7;
             lds = std::max(lds, front_lds_bytes(p->gA, p->npol));
         }
-        LF.push_back({multi_front_fn(b->npol, v.kind, v.pfb, v.L), use_graph ? wg_max : wg,
+        LF.push_back({multi_front_fn(b->npol, v.kind, v.pfb, v.L, v.pt), use_graph ? wg_max : wg,
                       kTilePoints / 16 * b->npol, lds, d_front + first, nf - first});
     }
     int nbk = 0;
@@ -1042,10 +1049,10 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             }
             wg += E.wgn;
             wg_max += (int)(p->ntilesB * max_chunks(p, F));
-            lds = std::max(lds, back_lds_bytes(p->gB, p->npol));
+            lds = std::max(lds, back_lds_bytes(p->gB, p->npol, p->prec_back));
             threads = back_tile(p->N1) / 16 * p->npol;
         }
-        LB.push_back({multi_back_fn(b->npol, v.L), use_graph ? wg_max : wg, threads, lds, d_back + first,
+        LB.push_back({multi_back_fn(b->npol, v.L, v.prec), use_graph ? wg_max : wg, threads, lds, d_back + first,
                       nbk - first});
     }
     // each column-pass group is followed by its own row passes, so that their

@@ -96,20 +96,41 @@ def quantise(v: np.ndarray) -> np.ndarray:
     return out
 
 
-def generate(spec: StreamSpec, t0: int, n: int) -> np.ndarray:
-    """Time samples ``[t0, t0 + n)`` of the stream as int8 ``[n, n_pol, 2]``."""
+def generate(spec: StreamSpec, t0: int, n: int, workers: int = 1) -> np.ndarray:
+    """Time samples ``[t0, t0 + n)`` of the stream as int8 ``[n, n_pol, 2]``.
+    ``workers`` > 1 generates the chunks on that many threads (numpy releases
+    the interpreter lock inside its array routines); the bytes are the same."""
     if n < 0 or t0 < 0:
         raise ValueError("negative window")
     out = np.empty((n, spec.n_pol, 2), dtype=np.int8)
+    pieces = []
     pos = 0
     while pos < n:
         t = t0 + pos
         c = t // GEN_CHUNK
         off = t - c * GEN_CHUNK
         take = min(GEN_CHUNK - off, n - pos)
-        out[pos:pos + take] = quantise(_chunk(spec, c)[off:off + take])
+        pieces.append((pos, c, off, take))
         pos += take
+
+    def fill(piece):
+        p, c, off, take = piece
+        out[p:p + take] = quantise(_chunk(spec, c)[off:off + take])
+
+    if workers > 1 and len(pieces) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(workers, len(pieces))) as ex:
+            list(ex.map(fill, pieces))
+    else:
+        for piece in pieces:
+            fill(piece)
     return out
+
+
+def default_workers() -> int:
+    """Generator threads: the cores this process may use, at most 16."""
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 # ---------------------------------------------------------------------------

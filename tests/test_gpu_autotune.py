@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_1411_0436_amd import pfbspec as pf
 from paper_1411_0436_amd import synth
-from tests.gpu_util import require_gpu, run_stream, within_fp32_bound
+from tests.gpu_util import rel_err, require_gpu, run_stream, within_fp32_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def test_autotune_returns_valid_setting_and_caches_it(tmp_path, monkeypatch):
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     f = lines[0].split()
-    assert f[0] == "pfbs-tune-v2" and f[1] == "gfx950" and "pfbspec " + f[2] == pf.version()
+    assert f[0] == "pfbs-tune-v3" and f[1] == "gfx950" and "pfbspec " + f[2] == pf.version()
     assert f[3:9] == ["8192", "8", "0", "2", "16", "0"]
     plan = pf.Plan(N, 8, n_pol=2, n_int=16, tune=1)
     info = plan.info()
@@ -51,3 +51,26 @@ def test_single_pass_shape_tunes_chunk_only(tmp_path, monkeypatch):
     monkeypatch.delenv("PFBS_TUNE_CACHE", raising=False)
     fields, sps = pf.autotune(block_samples=256 * 1024, N=1024, P=8, n_pol=1, n_int=64)
     assert sps > 0 and fields["split_n2"] == 0 and fields["col_run"] == 0
+
+
+def test_tuned_fp32_largest_mode_stays_within_1e5(tmp_path, monkeypatch):
+    """Whatever split the tuner picks for an FP32 plan at N = 2^19, the plan
+    keeps the largest mode's first dump within 1e-5 of the oracle: from 2^18
+    channels the FP32 row pass runs in FP64, where a strong tone's row would
+    otherwise carry more than 1e-5 of rounding."""
+    require_gpu()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PFBS_TUNE_CACHE", str(cache))
+    N = 1 << 19
+    fields, sps = pf.autotune(N=N, P=8, n_pol=2, n_int=64, precision=pf.PREC_FP32, max_candidates=12)
+    assert sps > 0 and fields["split_n2"] in (0, 128, 256, 512), fields
+    plan = pf.Plan(N, 8, n_pol=2, n_int=64, tune=1)
+    info = plan.info()
+    assert info["row_arith"] == 3
+    assert fields["split_n2"] in (0, info["split_n2"])
+    blk = 1 << 26
+    x = synth.generate(synth.spec_c3(), 0, blk, workers=synth.default_workers())
+    dumps, _, _ = run_stream(plan, x, [blk // N])
+    plan.close()
+    ref = oracle.integrate(x, N, 8, oracle.taps(N, 8), False, 0, 64, synth.default_workers())
+    assert rel_err(dumps[0], ref).max() <= 1e-5
