@@ -256,19 +256,18 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 #pragma unroll
             for (int pp = 0; pp < NPOL; ++pp) y[s][pp] = make_float2(0.f, 0.f);
         // uniform bases, 32-bit unsigned per-lane offsets
-        // buffer loads: uniform frame / tap-row base in a scalar descriptor,
-        // 32-bit per-lane offsets (no 64-bit address per load and tap held in
-        // vector registers)
-        const unsigned rest = (unsigned)(N - n1_0);   // points from the tile's first column to the frame end
+        // uniform bases, 32-bit unsigned per-lane offsets (global loads
+        // measured faster here than buffer loads: C2 column pass 131 against
+        // 137 us, split-FP16 at N=2^19 761 against 908 us)
         auto tap_loads = [&](int p, W4 (&w4)[PTS / 4], float4 (&h4)[PTS / 4]) {
-            const Rsrc fr = make_rsrc(frame_ptr<NPOL>(a.fr, j + p, N) + n1_0, rest * (unsigned)sizeof(W));
-            const Rsrc hr = make_rsrc(a.taps + (long long)p * N + n1_0, rest * 4u);
+            const W *fb = frame_ptr<NPOL>(a.fr, j + p, N) + n1_0;
+            const float *hb = a.taps + (long long)p * N + n1_0;
 #pragma unroll
             for (int g = 0; g < PTS / 4; ++g) {
                 const int q = tid + NB * g;
                 const unsigned n = (unsigned)(4 * (q & (G::T / 4 - 1)) + N1 * (q >> (G::logT - 2)));
-                w4[g] = buf_load<W4>(fr, n * (unsigned)sizeof(W));
-                if (PFB) h4[g] = buf_load<float4>(hr, n * 4u);
+                w4[g] = *reinterpret_cast<const W4 *>(fb + n);
+                if (PFB) h4[g] = *reinterpret_cast<const float4 *>(hb + n);
             }
         };
         W4 w4[PTS / 4];
@@ -414,7 +413,10 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
             for (int s = 0; s < 4 * GRP; ++s)
 #pragma unroll
                 for (int pp = 0; pp < NPOL; ++pp) y[h][s][pp] = make_float2(0.f, 0.f);
-        const unsigned rest = (unsigned)(N - n1_0);
+        // buffer loads: uniform frame / tap-row base in a scalar descriptor,
+        // 32-bit per-lane offsets (no 64-bit address per load held in vector
+        // registers; N=2^19 column pass 658 -> 522 us against global loads)
+        const unsigned rest = (unsigned)(N - n1_0);   // points from the tile's first column to the frame end
         auto frame_loads = [&](long long f, W4 (&w4)[GRP]) {
             const Rsrc fr = make_rsrc(frame_ptr<NPOL>(a.fr, min(f, f_last), N) + n1_0, rest * (unsigned)sizeof(W));
 #pragma unroll

@@ -173,7 +173,7 @@ hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipS
 
 hipError_t init_fourstep(int lds_limit) {
     hipError_t e0 = init_fourstep_p<0>(lds_limit), e1 = init_fourstep_p<1>(lds_limit),
-               e2 = init_fourstep_p<2>(lds_limit), e3 = init_back_p<3>(lds_limit);
+               e2 = init_fourstep_p<2>(lds_limit), e3 = init_back_p<3>(160 * 1024);
     return e0 != hipSuccess ? e0 : (e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3));
 }
 

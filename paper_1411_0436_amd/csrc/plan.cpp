@@ -413,7 +413,9 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->pair = p->fourstep && p->pfb && p->prec_front == PFBS_PREC_FP32 && g_pair_ok[dev] &&
               p->gA.L <= 256 && (int64_t)p->P * p->N >= (int64_t(1) << 21) &&
               2 * front_lds_bytes(p->gA, p->npol) <= (size_t)kPairLds;
-    // tap loop: unrolled where measured faster (the two-spectra column kernel)
+    // tap loop: unrolled where measured faster (the two-spectra column
+    // kernel: N=2^19 column pass 570 -> 539 us; the one-spectrum column
+    // kernel at N=2^15 180 against 131 us rolled)
     if (p->tap_unroll == 0) p->tap_unroll = p->pair ? 1 : 2;
     p->out_stokes = desc->output == PFBS_OUT_STOKES;
     p->out_shift = desc->fftshift;

@@ -56,6 +56,7 @@ def _create(**kw):
     dict(N=1024, P=8, n_pol=1, output=1),  # Stokes needs two polarisations
     dict(N=1024, P=8, output=5),
     dict(N=1024, P=8, fftshift=2),
+    dict(N=1024, P=8, tap_unroll=3),
     dict(N=1024, P=8, split_n2=256),      # single-pass size with a split
     dict(N=1 << 15, P=8, split_n2=100),
     dict(N=1 << 15, P=8, split_n2=2048),  # N1 = 16 too small
