@@ -199,6 +199,26 @@ pfbs_status pfbs_execute(pfbs_plan *plan, const void *d_block, int64_t n_time_sa
                          float *d_dumps, int64_t dump_capacity, int64_t *n_dumps_written,
                          void *stream);
 
+/* pfbs_execute for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results (bit for bit) and errors as pfbs_execute, but the plan's
+ * own intermediate and partial-sum buffers are not used or grown: the work
+ * goes through one fixed scratch array of 128 MiB per device (a file-scope
+ * device array of the library, held by every device the library runs on
+ * until the process ends), and the call makes no hipMalloc, hipFree or other
+ * allocating call (kernel timing is skipped).  A block whose partial sums
+ * (4 * n_prod * N bytes per chunk of spectra it touches) plus one chunk of
+ * the two-pass intermediate (8 * n_pol * N bytes per spectrum of a chunk) do
+ * not fit in 128 MiB is rejected with PFBS_ERR_INVALID before anything is
+ * queued (use smaller blocks, or a smaller chunk in the plan).  The scratch
+ * array is shared by every such call on one device and keeps the last
+ * call's contents; each call writes what it reads, so nothing needs clearing,
+ * but calls that overlap on one device (other streams, other plans or
+ * threads) race on it and must be serialised by the caller. */
+pfbs_status pfbs_execute_noalloc(pfbs_plan *plan, const void *d_block, int64_t n_time_samples,
+                                 float *d_dumps, int64_t dump_capacity, int64_t *n_dumps_written,
+                                 void *stream);
+
 /* Write the partial integration (spectra accumulated since the last dump) to
  * d_partial (device, float [n_prod][N]) and its spectrum count to *n_spectra
  * (host).  The plan's state is unchanged. */

@@ -84,6 +84,14 @@ int64_t tw16_count(const Geo &g) {
 
 std::mutex g_init_mu;
 bool g_init_done[64];
+
+// Scratch memory of pfbs_execute_noalloc: a file-scope device array (each
+// device the library runs on holds its own copy until the process ends).  In
+// host code its name is not a device address; the address comes from
+// hipGetSymbolAddress, taken once per device at its first plan creation.
+constexpr size_t kNoAllocScratch = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+void *g_scratch_ptr[64];
 // Column pass on two spectra per workgroup step: its LDS (twice the one-spectrum
 // kernel's, up to 140 KB) is available on the device.
 bool g_pair_ok[64];
@@ -357,6 +365,10 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
         if (!g_init_done[dev]) {
             hipError_t e = kernels_init();
             if (e != hipSuccess) return hip_fail(nullptr, e, "kernel attributes");
+            void *sp = nullptr;
+            e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+            g_scratch_ptr[dev] = sp;
             g_pair_ok[dev] = init_fourstep_pair(kPairLds);
             g_init_done[dev] = true;
         }
@@ -567,8 +579,16 @@ struct Prepared {
 // Validate the block, size the scratch buffers and compute every launch's
 // arguments.  Changes no stream state.  one_group: the whole block's
 // intermediate in one column pass / row pass pair (batched launches).
+// Scratch of one execute: the two-pass intermediate and the chunk partial sums.
+struct Scratch {
+    float2 *Z;
+    size_t Zcap;      // float2 elements
+    float *part;
+    size_t partcap;   // floats
+};
+
 pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps, int64_t cap,
-                    bool one_group, Prepared &w) {
+                    bool one_group, Prepared &w, void *fixed = nullptr, size_t fixed_bytes = 0) {
     pfbs_status st = check_block(p, d_block, n);
     if (st != PFBS_OK) return st;
     w.F = n / p->N;
@@ -599,14 +619,33 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
     ch.j_hi = j_hi;
     ch.gid_lo = gid_lo;
     ch.gid0 = gid_lo;
-    size_t zneed = 0;
-    if (p->fourstep) {
-        const int64_t gs = one_group ? (j_hi - j_lo + p->G)
-                                     : std::min<int64_t>(p->group_spectra, j_hi - j_lo + p->G);
-        zneed = (size_t)(gs + p->G) * p->npol * p->N;
+    Scratch sc;
+    const size_t part_floats = (size_t)n_chunks * p->nprod * p->N;
+    if (fixed) {
+        // a caller-independent fixed buffer (no allocation): the partial sums
+        // first, the intermediate in the rest; groups are sized to fit it
+        const size_t part_bytes = (part_floats * sizeof(float) + 255) & ~(size_t)255;
+        const size_t zmin = p->fourstep ? (size_t)p->G * p->npol * p->N * sizeof(float2) : 0;
+        if (part_bytes + zmin > fixed_bytes)
+            return fail(PFBS_ERR_INVALID,
+                        "block needs %zu bytes of scratch (%zu of partial sums, at least %zu of intermediate); "
+                        "the allocation-free entry point has %zu: use smaller blocks or a smaller chunk",
+                        part_bytes + zmin, part_bytes, zmin, fixed_bytes);
+        sc.part = reinterpret_cast<float *>(fixed);
+        sc.partcap = part_floats;
+        sc.Z = reinterpret_cast<float2 *>(reinterpret_cast<char *>(fixed) + part_bytes);
+        sc.Zcap = p->fourstep ? (fixed_bytes - part_bytes) / sizeof(float2) : 0;
+    } else {
+        size_t zneed = 0;
+        if (p->fourstep) {
+            const int64_t gs = one_group ? (j_hi - j_lo + p->G)
+                                         : std::min<int64_t>(p->group_spectra, j_hi - j_lo + p->G);
+            zneed = (size_t)(gs + p->G) * p->npol * p->N;
+        }
+        st = ensure_scratch(p, zneed, part_floats);
+        if (st != PFBS_OK) return st;
+        sc = {p->Z, p->Zcap, p->part, p->partcap};
     }
-    st = ensure_scratch(p, zneed, (size_t)n_chunks * p->nprod * p->N);
-    if (st != PFBS_OK) return st;
 
     FrontArgs fa;
     memset(&fa, 0, sizeof fa);
@@ -619,9 +658,9 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
     fa.P = p->P;
     fa.ntiles = p->ntilesA;
     fa.ch = ch;
-    fa.Z = p->Z;
+    fa.Z = sc.Z;
     fa.tw4 = p->tw4;
-    fa.part = p->part;
+    fa.part = sc.part;
     fa.pt = tap_variant(p->pfb, p->P, p->tap_unroll == 1);
     if (!p->fourstep) {
         w.single = fa;
@@ -629,18 +668,18 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
     } else {
         BackArgs ba;
         memset(&ba, 0, sizeof ba);
-        ba.Z = p->Z;
+        ba.Z = sc.Z;
         ba.g = p->gB;
         ba.N = p->N;
         ba.N1 = p->N1;
         ba.N2 = p->N2;
         ba.ntiles = p->ntilesB;
         ba.ch = ch;
-        ba.part = p->part;
+        ba.part = sc.part;
         // groups of whole chunks whose intermediate fits the Z buffer
         const int64_t zlimit =
             one_group ? (j_hi - j_lo + p->G)
-                      : std::min<int64_t>((int64_t)(p->Zcap / ((size_t)p->npol * p->N)),
+                      : std::min<int64_t>((int64_t)(sc.Zcap / ((size_t)p->npol * p->N)),
                                           std::max<int64_t>(p->group_spectra, p->G));
         int64_t g0 = gid_lo;
         while (g0 <= gid_hi) {
@@ -683,7 +722,7 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
     }
     ReduceArgs &ra = w.ra;
     memset(&ra, 0, sizeof ra);
-    ra.part = p->part;
+    ra.part = sc.part;
     ra.carried_in = p->carried[p->ccur];
     ra.carried_out = p->carried[p->ccur ^ 1];
     ra.out = d_dumps;
@@ -705,7 +744,15 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
     return PFBS_OK;
 }
 
-pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s) {
+pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s, bool may_time = true) {
+    // kernel timing creates events on demand; the allocation-free path never times
+    const uint32_t timing = p->timing;
+    if (!may_time) p->timing = 0;
+    struct Restore {
+        pfbs_plan *p;
+        uint32_t t;
+        ~Restore() { p->timing = t; }
+    } restore{p, timing};
     if (w.any) {
         if (!p->fourstep) {
             PFBS_HIP(p, timed(p, 0, s, [&] { return launch_front(w.single, p->npol, p->pfb, true, p->prec_front, w.single_chunks, s); }));
@@ -747,6 +794,23 @@ pfbs_status pfbs_execute(pfbs_plan *p, const void *d_block, int64_t n, float *d_
     if (st != PFBS_OK) return st;
     *n_written = 0;
     st = launch_prepared(p, w, (hipStream_t)stream);
+    if (st != PFBS_OK) return st;
+    commit(p, w);
+    *n_written = w.nd_out;
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_execute_noalloc(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps, int64_t cap,
+                                 int64_t *n_written, void *stream) {
+    if (!n_written) return fail(PFBS_ERR_INVALID, "n_dumps_written is NULL");
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    void *fixed = g_scratch_ptr[p->device];
+    if (!fixed) return fail(PFBS_ERR_STATE, "no scratch address for device %d", p->device);
+    Prepared w;
+    pfbs_status st = prepare(p, d_block, n, d_dumps, cap, false, w, fixed, kNoAllocScratch);
+    if (st != PFBS_OK) return st;
+    *n_written = 0;
+    st = launch_prepared(p, w, (hipStream_t)stream, false);
     if (st != PFBS_OK) return st;
     commit(p, w);
     *n_written = w.nd_out;

@@ -28,6 +28,7 @@ EXPORTS = (
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
     "pfbs_autotune", "pfbs_host_alloc", "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push",
     "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan", "pfbs_version", "pfbs_plan_timing_kinds",
+    "pfbs_execute_noalloc",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
     L.pfbs_dumps_in.argtypes = [vp, i64]
     L.pfbs_dumps_in.restype = i64
     L.pfbs_execute.argtypes = [vp, vp, i64, vp, i64, pi64, vp]
+    L.pfbs_execute_noalloc.argtypes = [vp, vp, i64, vp, i64, pi64, vp]
     L.pfbs_flush.argtypes = [vp, vp, pi64, vp]
     L.pfbs_plan_reset.argtypes = [vp]
     L.pfbs_debug_pfb.argtypes = [vp, vp, i64, vp, i64, pi64, vp]
@@ -116,6 +118,7 @@ def load(path: str = LIB_PATH):
     L.pfbs_hstream_plan.argtypes = [vp]
     L.pfbs_hstream_plan.restype = vp
     for name in ("pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_execute",
+                 "pfbs_execute_noalloc",
                  "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
                  "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy",
                  "pfbs_plan_timing", "pfbs_plan_timing_read", "pfbs_autotune", "pfbs_host_alloc",
@@ -227,6 +230,17 @@ class Plan:
         _check(self._lib.pfbs_execute(self._h, block.data_ptr(), n,
                                       None if dumps is None else dumps.data_ptr(), cap,
                                       ctypes.byref(out), _stream_ptr(stream)))
+        return out.value
+
+    def execute_noalloc(self, block, dumps=None, stream=None) -> int:
+        """execute() through pfbs_execute_noalloc: the library's fixed scratch
+        array instead of the plan's buffers; no device allocation."""
+        n = block.numel() // (2 * self.n_pol)
+        cap = 0 if dumps is None else dumps.numel() // (self.n_prod * self.N)
+        out = ctypes.c_int64(0)
+        _check(self._lib.pfbs_execute_noalloc(self._h, block.data_ptr(), n,
+                                              None if dumps is None else dumps.data_ptr(), cap,
+                                              ctypes.byref(out), _stream_ptr(stream)))
         return out.value
 
     def flush(self, partial, stream=None) -> int:
