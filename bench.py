@@ -387,7 +387,7 @@ def time_path(w, prec_name, dev_blocks, args):
     plan = pf.Plan(N, w["P"], mode=pf.MODE_DIRECT if w["direct"] else pf.MODE_PFB, n_pol=w["n_pol"],
                    n_int=w["n_int"], split_n2=args.split_n2, chunk=args.chunk,
                    group_bytes=args.group_mb << 20, precision=PRECISIONS[prec_name],
-                   tap_unroll=args.tap_unroll)
+                   tap_unroll=args.tap_unroll, col_pair=args.col_pair)
     info = plan.info()
     cap = max(plan.dumps_in(w["block"]) + 1, 2)
     dumps = torch.empty((cap, plan.n_prod, N), dtype=torch.float32, device="cuda")
@@ -470,7 +470,7 @@ def bench_stream(args):
         if ref is not None:
             r["max_rel_err"] = first_dump_error(w, PRECISIONS[p], dev_blocks, ref, split_n2=args.split_n2,
                                                 chunk=args.chunk, group_bytes=args.group_mb << 20,
-                                                tap_unroll=args.tap_unroll)
+                                                tap_unroll=args.tap_unroll, col_pair=args.col_pair)
         paths[p] = r
         print("bench: %s %.2f Gsamples/s%s" % (p, r["value"], "" if ref is None else
                                                 ", first-dump error %.3g" % r["max_rel_err"]),
@@ -568,6 +568,7 @@ def main():
                     help="c5: time samples per sub-band per block (a multiple of 2^19)")
     ap.add_argument("--split-n2", type=int, default=0)
     ap.add_argument("--tap-unroll", type=int, default=0, help="pre-filter tap loop (0 auto, 1 unrolled, 2 loop)")
+    ap.add_argument("--col-pair", type=int, default=0, help="two-spectra column kernel (0 auto, 1 on, 2 off)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0, help="override the workload's block count")
     ap.add_argument("--group-mb", type=int, default=0, help="bound on the two-pass intermediate (MiB)")

@@ -125,10 +125,10 @@ typedef enum { PFBS_OUT_PRODUCTS = 0, PFBS_OUT_STOKES = 1 } pfbs_output;
  *                 batched plans: 0 only;
  *   stream_z    : 1 = streaming (non-temporal) stores and loads of the
  *                 two-pass intermediate, 0 = ordinary ones;
- *   tap_unroll  : see the field (speed only; the same arithmetic in the same
- *                 order either way, so the same bits).
- * chunk, split_n2, group_bytes, col_run, stream_z and tap_unroll only change
- * speed, never results beyond FP32 rounding order.
+ *   tap_unroll, col_pair: see the fields (speed only; the same arithmetic in
+ *                 the same order either way, so the same bits).
+ * chunk, split_n2, group_bytes, col_run, stream_z, tap_unroll and col_pair
+ * only change speed, never results beyond FP32 rounding order.
  * With tune = 1 they are taken from the autotune cache when it holds an
  * entry for this device and shape (see pfbs_autotune); with tune = 2 a
  * missing entry is measured first.                                          */
@@ -152,7 +152,9 @@ typedef struct {
     int32_t fftshift;   /* 1: channels in shifted order, k' = (k + N/2) mod N */
     int32_t tap_unroll; /* pre-filter tap loop: 0 automatic, 1 unrolled at compile
                            time (P = 4 or 8), 2 a loop over P at run time */
-    int32_t pad_;
+    int32_t col_pair;   /* column pass on two spectra per workgroup step (pre-filter
+                           with 4-point columns of at most 256, PFB mode): 0
+                           automatic, 1 where it applies, 2 never */
 } pfbs_plan_desc;
 
 /* Create a plan (FP32 arithmetic; Section 4, initialisation: coefficients are
@@ -276,7 +278,7 @@ pfbs_status pfbs_plan_timing_kinds(pfbs_plan *plan, uint32_t kinds);
 pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches, int32_t n);
 
 /* Autotuner.  Times candidate settings of the speed-only fields (split_n2,
- * chunk, col_run, stream_z, tap_unroll) for the plan shape in *desc on its device, each
+ * chunk, col_run, stream_z, tap_unroll, col_pair) for the plan shape in *desc on its device, each
  * on the same synthetic stream of device blocks of block_samples time samples
  * (a positive multiple of N; 0 = 2^24; as many distinct blocks as make at
  * least 512 MB, at most 16, so the input streams from HBM and not from the
@@ -286,7 +288,7 @@ pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches
  * *best_samples_per_s (may be NULL).  At most max_candidates settings are
  * timed (0 = all).  If the environment variable PFBS_TUNE_CACHE names a file,
  * the result is appended to it as one text line
- *   pfbs-tune-v3 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z tap_unroll samples_per_s
+ *   pfbs-tune-v3 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z tap_unroll col_pair samples_per_s
  * (version: the source digest of pfbs_version, so a rebuilt library with
  * changed kernels does not reuse old measurements)
  * and later plans created with tune != 0 reuse the newest matching line.

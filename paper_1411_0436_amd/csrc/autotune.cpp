@@ -40,16 +40,16 @@ std::string device_arch() {
 struct Line {
     std::string arch, version;
     long long N, n_int, block, split;
-    int P, mode, npol, prec, chunk, col_run, stream_z, tap_unroll;
+    int P, mode, npol, prec, chunk, col_run, stream_z, tap_unroll, col_pair;
     double sps;
 };
 
 bool parse(const char *s, Line &l) {
     char tag[32], arch[64], ver[64];
-    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %lf", tag, arch, ver, &l.N, &l.P,
-                   &l.mode, &l.npol, &l.n_int, &l.prec, &l.block, &l.split, &l.chunk, &l.col_run,
-                   &l.stream_z, &l.tap_unroll, &l.sps);
-    if (n != 16 || strcmp(tag, "pfbs-tune-v3") != 0) return false;
+    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %d %lf", tag, arch, ver, &l.N,
+                   &l.P, &l.mode, &l.npol, &l.n_int, &l.prec, &l.block, &l.split, &l.chunk, &l.col_run,
+                   &l.stream_z, &l.tap_unroll, &l.col_pair, &l.sps);
+    if (n != 17 || strcmp(tag, "pfbs-tune-v3") != 0) return false;
     l.arch = arch;
     l.version = ver;
     return true;
@@ -87,9 +87,9 @@ void cache_append(const pfbs_plan_desc *d, int64_t block, const pfbs_plan_desc *
     std::lock_guard<std::mutex> lk(g_cache_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "pfbs-tune-v3 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %.6e\n", device_arch().c_str(),
-            PFBS_SOURCE_DIGEST, (long long)d->N, d->P, d->mode, d->n_pol, (long long)d->n_int, d->precision, (long long)block,
-            (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, b->tap_unroll, sps);
+    fprintf(f, "pfbs-tune-v3 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %d %.6e\n", device_arch().c_str(),
+            PFBS_SOURCE_DIGEST, (long long)d->N, d->P, d->mode, d->n_pol, (long long)d->n_int, d->precision,
+            (long long)block, (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, b->tap_unroll, b->col_pair, sps);
     fclose(f);
 }
 
@@ -152,6 +152,7 @@ pfbs_status tune_lookup(const pfbs_plan_desc *desc, bool measure_if_missing, pfb
         out->col_run = l.col_run;
         out->stream_z = l.stream_z;
         out->tap_unroll = l.tap_unroll;
+        out->col_pair = l.col_pair;
         return PFBS_OK;
     }
     if (!measure_if_missing) return PFBS_OK;

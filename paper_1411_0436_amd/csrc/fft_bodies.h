@@ -33,7 +33,7 @@ __device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
     // column and butterfly owned in the last radix-16 pass
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
     MfmaW Wm{};
-    if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
+    if constexpr (PREC != 0) Wm = mfma_operands_load(a.g.mw, lt & 63);
 
     float acc[BINS][NP];
 #pragma unroll
@@ -243,7 +243,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     // W_N^(n1 k2) of this thread's column, k2 = bb + r*L/16
     const float2 *tw4 = a.tw4 + (unsigned)((n1_0 + c_own) * L + bb_own);
     MfmaW Wm{};
-    if constexpr (PREC != 0) Wm = mfma_dft16_operands(lt & 63);
+    if constexpr (PREC != 0) Wm = mfma_operands_load(a.g.mw, lt & 63);
 
     // pre-filter work item q: four consecutive columns 4*(q mod T/4) .. +3 of
     // row n2 = q / (T/4), read with one 16-byte access per frame and per tap row
@@ -335,7 +335,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
         }
         __syncthreads();
         float2 v[16];
-        fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, true);
+        fft_plane_p<G, PREC, true>(sre, sim, pol, lt, a.g.tw, Wm, v, true);
         // ---- twiddle W_N^(n1 k2), back to LDS in natural order (each thread
         // rewrites the positions it has just read)
 #pragma unroll
@@ -366,8 +366,9 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
     }
 }
 
-// Column pass with pre-filter, FP32, two consecutive spectra j and j+1 per
-// workgroup step (twice the threads and LDS of front_cols_body).  The
+// Column pass with pre-filter, two consecutive spectra j and j+1 per
+// workgroup step (twice the threads and LDS of front_cols_body), the FFT in
+// any precision of front_cols_body.  The
 // pre-filter reads most of its bytes from L2 (P frames and P tap rows per
 // point), so each thread filters its points for both spectra at once: one
 // load of tap row p serves both, and the frames slide (frame j+p+1 is the
@@ -375,7 +376,7 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 // spectra instead of 2P.  Each half of the workgroup then transforms and
 // stores one spectrum, exactly as front_cols_body does (same arithmetic in
 // the same order, so the same bits).
-template <int NPOL, int L, int PT = 0>
+template <int NPOL, int L, int PT = 0, int PREC = 0>
 __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid, int nblk) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
@@ -400,6 +401,7 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
     const float2 *tw4 = a.tw4 + (unsigned)((n1_0 + c_own) * L + bb_own);
     MfmaW Wm{};
+    if constexpr (PREC != 0) Wm = mfma_operands_load(a.g.mw, lt & 63);
 
     for (long long j = js; j < je; j += 2) {
         const bool two = j + 1 < je;
@@ -501,7 +503,7 @@ __device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid
         }
         __syncthreads();
         float2 v[16];
-        fft_plane_p<G, 0>(sre, sim, pol, lt, a.g.tw, Wm, v, true);
+        fft_plane_p<G, PREC, true>(sre, sim, pol, lt, a.g.tw, Wm, v, true);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int k2 = bb_own + r * G::L16;
@@ -564,7 +566,7 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
     const int k2_0 = tile * G::T;
     const int c_own = lt >> (G::logL - 4), bb_own = lt & (G::L16 - 1);
     MfmaW Wm{};
-    if constexpr (FftPrec<PREC>::IN_LDS) Wm = mfma_dft16_operands(lt & 63);
+    if constexpr (FftPrec<PREC>::IN_LDS) Wm = mfma_operands_load(a.g.mw, lt & 63);
 
     float acc[BINS][NP];
 #pragma unroll

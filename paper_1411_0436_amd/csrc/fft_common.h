@@ -343,13 +343,16 @@ __device__ __forceinline__ void fft_plane(T *sre, T *sim, int pol, int lt, const
 // hi + lo pairs (x = hi + lo + O(2^-22 x)) and sums Wlo*hi + Whi*lo + Whi*hi.
 // The scale is undone exactly on the FP32 outputs.
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct MfmaW {
     half8 hr, hi, lr, li;   // hi and lo parts of the Re-row and Im-row operands
 };
 
-// Operands of lane `lane`, from W16^e = cos(pi e/8) - i sin(pi e/8) in double.
+// Operands of lane `lane`, from W16^e = cos(pi e/8) - i sin(pi e/8) in double
+// (run once per plan by the table kernel; the FFT kernels load the result).
 __device__ __forceinline__ MfmaW mfma_dft16_operands(int lane) {
     const int m = lane & 15, kb = lane >> 4;
     MfmaW w;
@@ -371,10 +374,22 @@ __device__ __forceinline__ MfmaW mfma_dft16_operands(int lane) {
     return w;
 }
 
+// The operands of lane `lane` from the plan's table: uint4 [64 lanes][4]
+// holding hr, hi, lr, li.
+__device__ __forceinline__ MfmaW mfma_operands_load(const uint4 *t, int lane) {
+    MfmaW w;
+    const uint4 *q = t + lane * 4;
+    w.hr = __builtin_bit_cast(half8, q[0]);
+    w.hi = __builtin_bit_cast(half8, q[1]);
+    w.lr = __builtin_bit_cast(half8, q[2]);
+    w.li = __builtin_bit_cast(half8, q[3]);
+    return w;
+}
+
 // Radix-16 pass I as in pass16 (same inputs, twiddles and output positions),
 // on the matrix cores.  Every pass, the last included, writes its outputs to
 // LDS; the last one's land in natural order.  PREC 1: MFMA_FP16, 2: FP16X2.
-template <class G, int I, int PREC>
+template <class G, int I, int PREC, bool WAVE = false>
 __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                             const MfmaW &W) {
     constexpr int Ns = G::r0 * (1 << (4 * I));
@@ -401,7 +416,7 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
             }
         }
     }
-    __syncthreads();
+    pass_sync<WAVE>();
 #pragma unroll
     for (int g = 0; g < GR; ++g) {
         // per-butterfly power-of-two scale (lanes n, n+16, n+32, n+48)
@@ -419,19 +434,27 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
             mx = fmaxf(mx, fmaxf(__uint_as_float(r32[0]), __uint_as_float(r32[1])));
         }
         const int sc = 15 - __builtin_amdgcn_frexp_expf(mx);
-        half8 bh, bl;
+        // (re, im) of a point are adjacent operand halves: one packed
+        // round-to-nearest conversion gives both hi parts, the lo parts are
+        // the exact FP32 remainders, packed the same way
+        uint4 uh, ul;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const float xr = __builtin_amdgcn_ldexpf(x[g][t].x, sc);
-            const float xi = __builtin_amdgcn_ldexpf(x[g][t].y, sc);
-            const _Float16 hr = (_Float16)xr, hi = (_Float16)xi;
-            bh[2 * t] = hr;
-            bh[2 * t + 1] = hi;
+            const float2v xs = {__builtin_amdgcn_ldexpf(x[g][t].x, sc), __builtin_amdgcn_ldexpf(x[g][t].y, sc)};
+            const half2v h = __builtin_convertvector(xs, half2v);
+            const unsigned hu = __builtin_bit_cast(unsigned, h);
+            unsigned lu = 0;
             if constexpr (PREC == 2) {
-                bl[2 * t] = (_Float16)(xr - (float)hr);
-                bl[2 * t + 1] = (_Float16)(xi - (float)hi);
+                const float2v r = xs - __builtin_convertvector(h, float2v);
+                lu = __builtin_bit_cast(unsigned, __builtin_convertvector(r, half2v));
             }
+            if (t == 0) { uh.x = hu; ul.x = lu; }
+            else if (t == 1) { uh.y = hu; ul.y = lu; }
+            else if (t == 2) { uh.z = hu; ul.z = lu; }
+            else { uh.w = hu; ul.w = lu; }
         }
+        const half8 bh = __builtin_bit_cast(half8, uh);
+        const half8 bl = __builtin_bit_cast(half8, ul);
         floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
         if constexpr (PREC == 2) {
             // small terms first: Wlo*hi, Whi*lo, then Whi*hi
@@ -453,25 +476,30 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
             sim[a] = __builtin_amdgcn_ldexpf(yi[i], -sc);
         }
     }
-    __syncthreads();
+    pass_sync<WAVE>();
 }
 
-template <class G, int I, int PREC>
+template <class G, int I, int PREC, bool WAVE = false>
 __device__ __forceinline__ void passes16_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                               const MfmaW &W) {
-    pass16_mfma<G, I, PREC>(sre, sim, pol, lt, tw, W);
-    if constexpr (I + 1 < G::n16) passes16_mfma<G, I + 1, PREC>(sre, sim, pol, lt, tw, W);
+    pass16_mfma<G, I, PREC, WAVE>(sre, sim, pol, lt, tw, W);
+    if constexpr (I + 1 < G::n16) passes16_mfma<G, I + 1, PREC, WAVE>(sre, sim, pol, lt, tw, W);
 }
 
 // The batched FFT of fft_plane with its radix-16 passes on the matrix cores;
 // the result is left in LDS in natural order (column c, bin k at idx(pol, c,
-// k)) after a workgroup barrier.
-template <class G, int PREC>
+// k)).  Without WAVE it ends with a workgroup barrier.  With WAVE (each column
+// within the lanes of one wave: a wave's 64 butterflies of every pass, the 4
+// groups of 16 that it gives the matrix cores, are whole columns) the passes
+// synchronise per wave only, and on return only the calling wave's columns
+// are known complete.
+template <class G, int PREC, bool WAVE = false>
 __device__ __forceinline__ void fft_plane_mfma(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                                const MfmaW &W) {
     static_assert(G::TPP % 64 == 0, "whole waves per polarisation");
-    if constexpr (G::r0 > 1) pass_small<G, G::r0, false>(sre, sim, pol, lt);
-    passes16_mfma<G, 0, PREC>(sre, sim, pol, lt, tw, W);
+    static_assert(!WAVE || G::WAVE_COLS, "wave-local passes need columns within one wave");
+    if constexpr (G::r0 > 1) pass_small<G, G::r0, WAVE>(sre, sim, pol, lt);
+    passes16_mfma<G, 0, PREC, WAVE>(sre, sim, pol, lt, tw, W);
 }
 
 // Precision dispatch: on return thread lt holds X_c[bb + r*L/16] in v (as
@@ -485,13 +513,16 @@ template <class G, int PREC> struct FftWave {
     static constexpr bool value = (PREC == 0 || PREC == 3) && G::WAVE_COLS;
 };
 
-template <class G, int PREC>
+// MFMA_WAVE (callers that afterwards touch only their own positions until a
+// workgroup barrier, as the column passes do): the matrix-core passes also
+// synchronise per wave where the geometry allows it.
+template <class G, int PREC, bool MFMA_WAVE = false>
 __device__ __forceinline__ void fft_plane_p(float *sre, float *sim, int pol, int lt, const float2 *tw,
                                             const MfmaW &W, float2 (&v)[16], bool want_regs) {
     if constexpr (PREC == 0) {
         fft_plane<G, FftWave<G, PREC>::value>(sre, sim, pol, lt, tw, v);
     } else {
-        fft_plane_mfma<G, PREC>(sre, sim, pol, lt, tw, W);
+        fft_plane_mfma<G, PREC, MFMA_WAVE && G::WAVE_COLS>(sre, sim, pol, lt, tw, W);
         if (want_regs) {
             const int c = lt >> (G::logL - 4), bb = lt & (G::L16 - 1);
 #pragma unroll

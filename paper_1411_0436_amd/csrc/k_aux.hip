@@ -258,6 +258,17 @@ __global__ void k_tw16(C *tw, int r0, int n16) {
     }
 }
 
+// Matrix-core operands of the radix-16 DFT (hi and lo FP16 parts of its real
+// form, from FP64), one row of four 16-byte values per lane.
+__global__ void k_mfma_w(uint4 *mw) {
+    const int lane = threadIdx.x;
+    const MfmaW w = mfma_dft16_operands(lane);
+    mw[lane * 4 + 0] = __builtin_bit_cast(uint4, w.hr);
+    mw[lane * 4 + 1] = __builtin_bit_cast(uint4, w.hi);
+    mw[lane * 4 + 2] = __builtin_bit_cast(uint4, w.lr);
+    mw[lane * 4 + 3] = __builtin_bit_cast(uint4, w.li);
+}
+
 // Four-step twiddles tw4[n1*N2 + k2] = W_N^(n1 k2), FP64 sincospi then FP32.
 __global__ void k_tw4(float2 *tw4, long long N1, long long N2) {
     const long long N = N1 * N2;
@@ -314,6 +325,11 @@ hipError_t launch_tables_taps(float *h, long long N, int P, int window, const do
 hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s) {
     const int logL = ilog2c(L);
     hipLaunchKernelGGL(k_tw16<float2>, dim3(64), dim3(256), 0, s, tw, 1 << (logL % 4), logL / 4);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_mfma(uint4 *mw, hipStream_t s) {
+    hipLaunchKernelGGL(k_mfma_w, dim3(1), dim3(64), 0, s, mw);
     return hipGetLastError();
 }
 

@@ -22,9 +22,9 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL, (ColsMinWaves<L, PREC>::va
     front_cols_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x, gridDim.x);
 }
 
-template <int NPOL, int L, int PT = 0>
+template <int NPOL, int L, int PT = 0, int PREC = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL * 2) void k_front_cols_pair(FrontArgs a) {
-    front_cols_pair_body<NPOL, L, PT>(a, blockIdx.x, gridDim.x);
+    front_cols_pair_body<NPOL, L, PT, PREC>(a, blockIdx.x, gridDim.x);
 }
 
 template <int NPOL, int L, int PREC>
@@ -126,15 +126,19 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, i
     const size_t lds = front_lds_bytes(a.g, npol);
     const dim3 grid(n_items * a.ntiles), block(kTilePoints / 16 * npol);
     if (a.pair) {
-        if (prec != 0 || !pfb) return hipErrorInvalidValue;
+        if (!pfb || prec < 0 || prec > 2) return hipErrorInvalidValue;
         const dim3 block2(2 * block.x);
         switch (a.g.L) {
-#define PFBS_PAIR(NP, LL)                                                                            \
-    switch (a.pt) {                                                                                  \
-    case 4: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 4>), grid, block2, 2 * lds, s, a); break;         \
-    case 8: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 8>), grid, block2, 2 * lds, s, a); break;         \
-    default: PFBS_LAUNCH((k_front_cols_pair<NP, LL>), grid, block2, 2 * lds, s, a); break;           \
+#define PFBS_PAIR_P(NP, LL, PR)                                                                          \
+    switch (a.pt) {                                                                                      \
+    case 4: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 4, PR>), grid, block2, 2 * lds, s, a); break;         \
+    case 8: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 8, PR>), grid, block2, 2 * lds, s, a); break;         \
+    default: PFBS_LAUNCH((k_front_cols_pair<NP, LL, 0, PR>), grid, block2, 2 * lds, s, a); break;        \
     }
+#define PFBS_PAIR(NP, LL)                                                                            \
+    if (prec == 0) { PFBS_PAIR_P(NP, LL, 0) }                                                       \
+    else if (prec == 1) { PFBS_PAIR_P(NP, LL, 1) }                                                  \
+    else { PFBS_PAIR_P(NP, LL, 2) }
 #define PFBS_CASE(LL)                                                                                \
     case LL:                                                                                         \
         if (npol == 2) {                                                                             \
@@ -146,6 +150,7 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, i
             PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
 #undef PFBS_PAIR
+#undef PFBS_PAIR_P
         default:
             return hipErrorInvalidValue;
         }
@@ -179,16 +184,19 @@ hipError_t init_fourstep(int lds_limit) {
 
 bool init_fourstep_pair(int lds_limit) {
     bool ok = true;
+#define PFBS_PAIR_FNS(LL, PR)                                                                                     \
+    reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 0, PR>),                                             \
+        reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 4, PR>),                                         \
+        reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 8, PR>),                                         \
+        reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 0, PR>),                                         \
+        reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 4, PR>),                                         \
+        reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 8, PR>)
 #define PFBS_CASE(LL)                                                                                           \
-    for (const void *fn : {reinterpret_cast<const void *>(k_front_cols_pair<2, LL>),                              \
-                           reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 4>),                           \
-                           reinterpret_cast<const void *>(k_front_cols_pair<2, LL, 8>),                           \
-                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL>),                              \
-                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 4>),                           \
-                           reinterpret_cast<const void *>(k_front_cols_pair<1, LL, 8>)})                          \
+    for (const void *fn : {PFBS_PAIR_FNS(LL, 0), PFBS_PAIR_FNS(LL, 1), PFBS_PAIR_FNS(LL, 2)})                                \
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess) ok = false;
     PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
+#undef PFBS_PAIR_FNS
     (void)hipGetLastError();
     return ok;
 }

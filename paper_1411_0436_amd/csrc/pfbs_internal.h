@@ -37,6 +37,7 @@ struct Geo {
     int T;                // sequences per workgroup step (tile points / L)
     const float2 *tw;     // radix-16 pass twiddles, passes concatenated
     const double2 *tw64;  // the same in FP64 (row pass in FP64 only, else null)
+    const uint4 *mw;      // matrix-core DFT-16 operands, [64 lanes][4] (matrix-core plans)
 };
 
 // Spectrum-chunk enumeration.  Dump d covers global spectra
@@ -181,6 +182,7 @@ hipError_t launch_tables_taps(float *h, long long N, int P, int window, const do
                               hipStream_t s);
 hipError_t launch_tables_tw16(float2 *tw, int L, hipStream_t s);
 hipError_t launch_tables_tw16_f64(double2 *tw, int L, hipStream_t s);
+hipError_t launch_tables_mfma(uint4 *mw, hipStream_t s);   // 64 lanes x 4 uint4
 hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_t s);
 // prec: 0 = FP32, 1 = matrix cores with an FP16 DFT matrix, 2 = hi + lo matrix
 hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int prec, int n_items,

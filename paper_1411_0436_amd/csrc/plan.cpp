@@ -126,6 +126,7 @@ struct pfbs_plan {
     float *taps;
     float2 *twA, *twB, *tw4;
     double2 *twB64;      // row-pass twiddles in FP64 (FP64 row pass only)
+    uint4 *mw;           // matrix-core DFT-16 operands (plans using the matrix cores)
     uint8_t *hist[2];
     int hcur;
     int64_t frame_bytes;
@@ -237,6 +238,7 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
     if (d->fftshift != 0 && d->fftshift != 1) return fail(PFBS_ERR_INVALID, "fftshift must be 0 or 1");
     if (d->tune < 0 || d->tune > 2) return fail(PFBS_ERR_INVALID, "tune must be 0, 1 or 2");
     if (d->tap_unroll < 0 || d->tap_unroll > 2) return fail(PFBS_ERR_INVALID, "tap_unroll must be 0, 1 or 2");
+    if (d->col_pair < 0 || d->col_pair > 2) return fail(PFBS_ERR_INVALID, "col_pair must be 0, 1 or 2");
     return PFBS_OK;
 }
 
@@ -274,7 +276,7 @@ hipError_t dalloc(pfbs_plan *p, T **ptr, size_t count) {
 }
 
 void free_plan_memory(pfbs_plan *p) {
-    void *bufs[] = {p->taps, p->twA, p->twB, p->twB64, p->tw4, p->hist[0], p->hist[1],
+    void *bufs[] = {p->taps, p->twA, p->twB, p->twB64, p->mw, p->tw4, p->hist[0], p->hist[1],
                     p->Z, p->part, p->carried[0], p->carried[1]};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -422,9 +424,14 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     // faster only where the tap table (P*N floats) overflows the 4 MB L2 of
     // an XCD (N = 2^19: column pass -8%; N <= 2^16: +3 to +6%), and with
     // columns of at most 256 (the 512 kernel spills registers).
-    p->pair = p->fourstep && p->pfb && p->prec_front == PFBS_PREC_FP32 && g_pair_ok[dev] &&
-              p->gA.L <= 256 && (int64_t)p->P * p->N >= (int64_t(1) << 21) &&
-              2 * front_lds_bytes(p->gA, p->npol) <= (size_t)kPairLds;
+    const bool pair_fits = p->fourstep && p->pfb && g_pair_ok[dev] && p->gA.L <= 256 &&
+                           2 * front_lds_bytes(p->gA, p->npol) <= (size_t)kPairLds;
+    // automatic: FP32 columns where the tap table overflows an XCD's L2 (the
+    // matrix-core column FFT spills registers in the 1024-thread workgroup:
+    // split-FP16 at N=2^19 1010 against 761 us one spectrum per step)
+    p->pair = pair_fits && (desc->col_pair == 1 ||
+                            (desc->col_pair == 0 && p->prec_front == PFBS_PREC_FP32 &&
+                             (int64_t)p->P * p->N >= (int64_t(1) << 21)));
     // tap loop: unrolled where measured faster (the two-spectra column
     // kernel: N=2^19 column pass 570 -> 539 us; the one-spectrum column
     // kernel at N=2^15 180 against 131 us rolled)
@@ -440,6 +447,13 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
         if ((e = dalloc(p, &p->taps, (size_t)p->P * p->N)) != hipSuccess) break;
         if ((e = dalloc(p, &p->twA, (size_t)tw16_count(p->gA))) != hipSuccess) break;
         p->gA.tw = p->twA;
+        if (p->prec_front == PFBS_PREC_MFMA_FP16 || p->prec_front == PFBS_PREC_MFMA_FP16X2 ||
+            p->prec_back == PFBS_PREC_MFMA_FP16 || p->prec_back == PFBS_PREC_MFMA_FP16X2) {
+            if ((e = dalloc(p, &p->mw, 64 * 4)) != hipSuccess) break;
+            if ((e = launch_tables_mfma(p->mw, s)) != hipSuccess) break;
+            p->gA.mw = p->mw;
+            p->gB.mw = p->mw;
+        }
         if (p->fourstep) {
             if ((e = dalloc(p, &p->twB, (size_t)tw16_count(p->gB))) != hipSuccess) break;
             p->gB.tw = p->twB;

@@ -49,7 +49,7 @@ class PlanDesc(ctypes.Structure):
         ("split_n2", ctypes.c_int64), ("group_bytes", ctypes.c_int64),
         ("col_run", ctypes.c_int32), ("stream_z", ctypes.c_int32),
         ("output", ctypes.c_int32), ("fftshift", ctypes.c_int32),
-        ("tap_unroll", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("tap_unroll", ctypes.c_int32), ("col_pair", ctypes.c_int32),
     ]
 
 
@@ -153,7 +153,7 @@ def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_P
               n_int: int = 1, precision: int = PREC_FP32, device: int = -1, custom_taps=None,
               tune: int = 0, chunk: int = 0, split_n2: int = 0, group_bytes: int = 0,
               col_run: int = 0, stream_z: int = 0, output: int = 0, fftshift: int = 0,
-              tap_unroll: int = 0):
+              tap_unroll: int = 0, col_pair: int = 0):
     """A PlanDesc; ``custom_taps`` (float64 numpy array) is kept alive on the
     returned object until the plan is created."""
     import numpy as np
@@ -161,7 +161,7 @@ def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_P
                  precision=precision, device=device, custom_taps=None, tune=tune,
                  chunk=chunk, split_n2=split_n2, group_bytes=group_bytes,
                  col_run=col_run, stream_z=stream_z, output=output, fftshift=fftshift,
-                 tap_unroll=tap_unroll)
+                 tap_unroll=tap_unroll, col_pair=col_pair)
     keep = None
     if custom_taps is not None:
         keep = np.ascontiguousarray(custom_taps, dtype=np.float64)
@@ -181,7 +181,7 @@ def autotune(block_samples: int = 0, max_candidates: int = 0, **desc_kw):
     sps = ctypes.c_double(0.0)
     _check(L.pfbs_autotune(ctypes.byref(d), block_samples, max_candidates, ctypes.byref(best),
                            ctypes.byref(sps)))
-    fields = ("split_n2", "chunk", "col_run", "stream_z", "tap_unroll")
+    fields = ("split_n2", "chunk", "col_run", "stream_z", "tap_unroll", "col_pair")
     return {f: getattr(best, f) for f in fields}, sps.value
 
 

@@ -145,3 +145,26 @@ def test_batch_rejects_matrix_core_precisions_and_output_forms():
         desc = pf.make_desc(N=4096, P=8, n_pol=2, n_int=4, **kw)
         with pytest.raises(pf.PfbsError):
             pf.Batch([desc])
+
+
+@pytest.mark.parametrize("prec,n_pol", [(X2, 2), (F16, 2), (X2, 1), (pf.PREC_FP32, 2)])
+@pytest.mark.parametrize("unroll", [1, 2])
+def test_two_spectra_column_kernel_equals_one_spectrum_kernel(prec, n_pol, unroll):
+    """The two-spectra column kernel (col_pair=1) runs the same pre-filter and
+    column FFT, in the same order, as the one-spectrum kernel (col_pair=2), in
+    every precision and with either tap loop: the dumps agree bit for bit,
+    with odd and even spectrum counts per block."""
+    N, P, ni = 262144, 8, 3
+    frames = [12, 11, 10]
+    x = synth.generate(synth.spec_subband(5, N), 7, N * sum(frames))
+    if n_pol == 1:
+        x = np.ascontiguousarray(x[:, :1, :])
+    out = []
+    for pair in (1, 2):
+        plan = pf.Plan(N, P, n_pol=n_pol, n_int=ni, precision=prec, split_n2=256, col_pair=pair,
+                       tap_unroll=unroll)
+        out.append(run_stream(plan, x, frames))
+        plan.close()
+    (d1, p1, c1), (d2, p2, c2) = out
+    assert d1.shape == d2.shape and d1.shape[0] == (5 + 11 + 10) // ni
+    assert np.array_equal(d1, d2) and np.array_equal(p1, p2) and c1 == c2
