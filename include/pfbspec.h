@@ -244,6 +244,28 @@ pfbs_status pfbs_debug_pfb(pfbs_plan *plan, const void *d_block, int64_t n_time_
 /* Test hook: copy the plan's FP32 filter taps h[P*N] to d_out (device). */
 pfbs_status pfbs_debug_taps(pfbs_plan *plan, float *d_out, void *stream);
 
+/* Test hook: copy one of the plan's device tables (all generated on the
+ * device in FP64 and rounded once, Section 4 initialisation) to d_out
+ * (device, capacity_bytes long); *bytes (host) receives its size, 0 when the
+ * plan has no such table (then nothing is copied).  With d_out NULL only the
+ * size is returned.  Tables:
+ *   TAPS        : float h[P*N];
+ *   TW_FIRST    : float2 radix-16 pass twiddles of the single pass or column
+ *                 pass, W_(16 Ns)^(k r) for k < Ns, r = 1..15, passes
+ *                 Ns = r0, 16 r0, ... concatenated (r0 = L / 16^floor(log16 L));
+ *   TW_ROWS     : the same for the row pass of the two-pass FFT;
+ *   TW_ROWS_F64 : double2, the same in FP64 (FP64 row pass only);
+ *   TW_STEP     : float2 four-step twiddles, [n1][k2] = W_N^(n1 k2);
+ *   MFMA        : the matrix-core DFT-16 operands, 64 lanes x 4 x 16 bytes. */
+#define PFBS_TABLE_TAPS 0
+#define PFBS_TABLE_TW_FIRST 1
+#define PFBS_TABLE_TW_ROWS 2
+#define PFBS_TABLE_TW_ROWS_F64 3
+#define PFBS_TABLE_TW_STEP 4
+#define PFBS_TABLE_MFMA 5
+pfbs_status pfbs_debug_table(pfbs_plan *plan, int32_t which, void *d_out, int64_t capacity_bytes,
+                             int64_t *bytes, void *stream);
+
 /* Read-only plan facts for callers and tests (host, no device call). */
 typedef struct {
     int64_t N;

@@ -90,5 +90,40 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(outdir: str, verbose: bool = False) -> str:
+    """The same library with the address and undefined-behaviour sanitizers
+    in its host code (device code is built as usual), linked into outdir.
+    For host-side tests without a GPU.  Returns the library path."""
+    os.makedirs(outdir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs, procs = [], []
+    version = ['-DPFBS_SOURCE_DIGEST="%s"' % source_digest()]
+    for src in SOURCES:
+        obj = os.path.join(outdir, src + ".o")
+        objs.append(obj)
+        cmd = [HIPCC] + FLAGS + san + version + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    errs = []
+    for cmd, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            errs.append(" ".join(cmd) + "\n" + out.decode(errors="replace"))
+    if errs:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
+    lib = os.path.join(outdir, "libpfbspec.so")
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "lib", "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang++"
+    cmd = [clang, "-shared", "-fPIC", "-fsanitize=address,undefined", "-o", lib] + objs + \
+          ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

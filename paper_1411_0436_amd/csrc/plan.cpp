@@ -140,6 +140,10 @@ struct pfbs_plan {
     // stream counters
     int64_t frames_seen, spectra_done, dumps_done;
     bool poisoned;
+    // host-side fault injection (PFBS_FAULT, read at plan creation): the
+    // n-th device allocation / kernel launch of this plan reports a failure
+    // instead of being made (0 = off)
+    int64_t fault_alloc, fault_launch;
     // optional kernel timing: (kind, start, stop) per launch since the last read
     uint32_t timing;     // bit k: time the launches of kernel kind k
     std::vector<hipEvent_t> ev_pool;
@@ -270,6 +274,7 @@ template <typename T>
 hipError_t dalloc(pfbs_plan *p, T **ptr, size_t count) {
     *ptr = nullptr;
     if (count == 0) count = 1;
+    if (p->fault_alloc > 0 && --p->fault_alloc == 0) return hipErrorOutOfMemory;  // injected
     hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
     if (e == hipSuccess) p->device_bytes += (int64_t)(count * sizeof(T));
     return e;
@@ -285,6 +290,7 @@ void free_plan_memory(pfbs_plan *p) {
 // Run one launch, bracketed by timing events when the plan measures kernels.
 template <typename F>
 hipError_t timed(pfbs_plan *p, int kind, hipStream_t s, F &&launch) {
+    if (p->fault_launch > 0 && --p->fault_launch == 0) return hipErrorLaunchFailure;  // injected
     if (!((p->timing >> kind) & 1u)) return launch();
     while (p->ev_pool.size() < p->ev_used + 2) {
         hipEvent_t e;
@@ -302,6 +308,19 @@ hipError_t timed(pfbs_plan *p, int kind, hipStream_t s, F &&launch) {
     p->ev_used += 2;
     p->recs.push_back({kind, i0});
     return hipSuccess;
+}
+
+// PFBS_FAULT = "alloc:<n>" or "launch:<n>" (n >= 1): the plan created while
+// it is set fails its n-th device allocation (hipErrorOutOfMemory) or its
+// n-th kernel launch (hipErrorLaunchFailure) on the host, without touching
+// the device, so that the error, poisoning and reset paths can be exercised.
+void parse_fault(pfbs_plan *p) {
+    p->fault_alloc = p->fault_launch = 0;
+    const char *f = getenv("PFBS_FAULT");
+    if (!f) return;
+    long long n = 0;
+    if (sscanf(f, "alloc:%lld", &n) == 1 && n > 0) p->fault_alloc = n;
+    else if (sscanf(f, "launch:%lld", &n) == 1 && n > 0) p->fault_launch = n;
 }
 
 pfbs_status ensure_scratch(pfbs_plan *p, size_t z_elems, size_t part_floats) {
@@ -379,6 +398,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     pfbs_plan *p = new (std::nothrow) pfbs_plan();
     if (!p) return fail(PFBS_ERR_NOMEM, "host allocation");
     p->magic = kMagic;
+    parse_fault(p);
     p->N = desc->N;
     p->pfb = desc->mode == PFBS_MODE_PFB;
     p->P = p->pfb ? desc->P : 1;
@@ -928,6 +948,30 @@ pfbs_status pfbs_debug_taps(pfbs_plan *p, float *d_out, void *stream) {
     PFBS_HIP(p, hipSetDevice(p->device));
     PFBS_HIP(p, hipMemcpyAsync(d_out, p->taps, (size_t)p->P * p->N * sizeof(float),
                                hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return PFBS_OK;
+}
+
+pfbs_status pfbs_debug_table(pfbs_plan *p, int32_t which, void *d_out, int64_t capacity_bytes, int64_t *bytes,
+                             void *stream) {
+    if (!plan_ok(p)) return fail(PFBS_ERR_STATE, "not a live plan");
+    if (!bytes) return fail(PFBS_ERR_INVALID, "bytes is NULL");
+    const void *src = nullptr;
+    size_t n = 0;
+    switch (which) {
+    case PFBS_TABLE_TAPS: src = p->taps; n = (size_t)p->P * p->N * sizeof(float); break;
+    case PFBS_TABLE_TW_FIRST: src = p->twA; n = (size_t)tw16_count(p->gA) * sizeof(float2); break;
+    case PFBS_TABLE_TW_ROWS: src = p->twB; n = p->twB ? (size_t)tw16_count(p->gB) * sizeof(float2) : 0; break;
+    case PFBS_TABLE_TW_ROWS_F64: src = p->twB64; n = p->twB64 ? (size_t)tw16_count(p->gB) * sizeof(double2) : 0; break;
+    case PFBS_TABLE_TW_STEP: src = p->tw4; n = p->tw4 ? (size_t)p->N * sizeof(float2) : 0; break;
+    case PFBS_TABLE_MFMA: src = p->mw; n = p->mw ? (size_t)64 * 4 * sizeof(uint4) : 0; break;
+    default: return fail(PFBS_ERR_INVALID, "unknown table %d", which);
+    }
+    *bytes = (int64_t)n;
+    if (n == 0 || !d_out) return PFBS_OK;
+    if ((int64_t)n > capacity_bytes)
+        return fail(PFBS_ERR_INVALID, "table needs %zu bytes, capacity %lld", n, (long long)capacity_bytes);
+    PFBS_HIP(p, hipSetDevice(p->device));
+    PFBS_HIP(p, hipMemcpyAsync(d_out, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return PFBS_OK;
 }
 

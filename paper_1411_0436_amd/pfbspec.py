@@ -19,6 +19,7 @@ WINDOW_HANN_SINC, WINDOW_RECT, WINDOW_CUSTOM = 0, 1, 2
 MODE_PFB, MODE_DIRECT = 0, 1
 PREC_FP32, PREC_MFMA_FP16, PREC_MFMA_FP16X2, PREC_MIXED = 0, 1, 2, 3
 OUT_PRODUCTS, OUT_STOKES = 0, 1
+TABLE_TAPS, TABLE_TW_FIRST, TABLE_TW_ROWS, TABLE_TW_ROWS_F64, TABLE_TW_STEP, TABLE_MFMA = range(6)
 
 # Every entry point declared in include/pfbspec.h.
 EXPORTS = (
@@ -28,7 +29,7 @@ EXPORTS = (
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
     "pfbs_autotune", "pfbs_host_alloc", "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push",
     "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan", "pfbs_version", "pfbs_plan_timing_kinds",
-    "pfbs_execute_noalloc",
+    "pfbs_execute_noalloc", "pfbs_debug_table",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -95,6 +96,7 @@ def load(path: str = LIB_PATH):
     L.pfbs_plan_reset.argtypes = [vp]
     L.pfbs_debug_pfb.argtypes = [vp, vp, i64, vp, i64, pi64, vp]
     L.pfbs_debug_taps.argtypes = [vp, vp, vp]
+    L.pfbs_debug_table.argtypes = [vp, i32, vp, i64, pi64, vp]
     L.pfbs_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.pfbs_last_error.restype = ctypes.c_char_p
     L.pfbs_version.restype = ctypes.c_char_p
@@ -118,7 +120,7 @@ def load(path: str = LIB_PATH):
     L.pfbs_hstream_plan.argtypes = [vp]
     L.pfbs_hstream_plan.restype = vp
     for name in ("pfbs_plan_create", "pfbs_plan_create_ex", "pfbs_plan_destroy", "pfbs_execute",
-                 "pfbs_execute_noalloc",
+                 "pfbs_execute_noalloc", "pfbs_debug_table",
                  "pfbs_flush", "pfbs_plan_reset", "pfbs_debug_pfb", "pfbs_debug_taps",
                  "pfbs_plan_get_info", "pfbs_batch_create", "pfbs_batch_execute", "pfbs_batch_destroy",
                  "pfbs_plan_timing", "pfbs_plan_timing_read", "pfbs_autotune", "pfbs_host_alloc",
@@ -261,6 +263,19 @@ class Plan:
 
     def debug_taps(self, out, stream=None):
         _check(self._lib.pfbs_debug_taps(self._h, out.data_ptr(), _stream_ptr(stream)))
+
+    def debug_table(self, which: int):
+        """One of the plan's device tables (TABLE_*) as a uint8 cuda tensor,
+        or None when the plan has none."""
+        import torch
+        n = ctypes.c_int64(0)
+        _check(self._lib.pfbs_debug_table(self._h, which, None, 0, ctypes.byref(n), _stream_ptr(None)))
+        if n.value == 0:
+            return None
+        out = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        _check(self._lib.pfbs_debug_table(self._h, which, out.data_ptr(), n.value, ctypes.byref(n),
+                                          _stream_ptr(None)))
+        return out
 
     def timing(self, enable: bool = True, kinds=None):
         """Time every launch (enable), or only the named kernel kinds."""

@@ -3,6 +3,10 @@
     python -m paper_1411_0436_amd.prof_summary stats KERNEL_STATS_CSV OUT --command "..."
         per-kernel calls / average / total time of a --kernel-trace --stats run;
 
+    python -m paper_1411_0436_amd.prof_summary sq OUT DIR [DIR ...] --match NAME
+        --workload W --precision P --command "..."
+        SQ instruction / wait counters per dispatch and per wave;
+
     python -m paper_1411_0436_amd.prof_summary traffic --fetch DIR --write DIR
         --copy-fetch DIR --copy-write DIR --match NAME --kind KIND
         --workload W --precision P OUT --command "..."
@@ -109,6 +113,39 @@ def cmd_traffic(a):
     _write(a.out, out)
 
 
+def cmd_sq(a):
+    """Per-dispatch SQ counters of the kernels whose name contains MATCH,
+    from one or more counter runs, with per-wave instruction counts."""
+    vals = collections.OrderedDict()
+    names = set()
+    for d in a.dirs:
+        for r in _counter_rows(d):
+            if a.match not in r["Kernel_Name"]:
+                continue
+            names.add(r["Kernel_Name"].replace("void ", "").split("(")[0])
+            key = r["Counter_Name"]
+            vals.setdefault(key, collections.defaultdict(float))[r.get("Dispatch_Id", r.get("Correlation_Id", "0"))] += \
+                float(r["Counter_Value"])
+    out = ["# rocprofv3 SQ counters per dispatch (summed over the counter's instances, averaged over dispatches)",
+           "# commands: %s" % a.command, "# workload: %s, precision: %s" % (a.workload, a.precision),
+           "# kernel sources sha1: %s" % kernel_digest(), "", "kernel: %s" % "; ".join(sorted(names))]
+    avg = {k: sum(v.values()) / max(1, len(v)) for k, v in vals.items()}
+    for k in sorted(avg):
+        out.append("  %-24s %.4g" % (k, avg[k]))
+    waves = avg.get("SQ_WAVES", 0.0)
+    if waves:
+        per = ", ".join("%s %.1f" % (lab, avg[c] / waves) for lab, c in
+                        (("VALU", "SQ_INSTS_VALU"), ("LDS", "SQ_INSTS_LDS"), ("VMEM read", "SQ_INSTS_VMEM_RD"),
+                         ("VMEM write", "SQ_INSTS_VMEM_WR"), ("SALU", "SQ_INSTS_SALU")) if c in avg)
+        out.append("  per wave: %s instructions" % per)
+    if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg and avg["SQ_WAVE_CYCLES"]:
+        out.append("  waiting on counters: %.0f %% of wave cycles" % (100.0 * avg["SQ_WAIT_INST_ANY"] / avg["SQ_WAVE_CYCLES"]))
+    if "SQ_LDS_BANK_CONFLICT" in avg and avg.get("SQ_ACTIVE_INST_LDS"):
+        out.append("  LDS bank-conflict cycles / LDS active cycles: %.2f"
+                   % (avg["SQ_LDS_BANK_CONFLICT"] / avg["SQ_ACTIVE_INST_LDS"]))
+    _write(a.out, out)
+
+
 def _write(path, lines):
     text = "\n".join(lines) + "\n"
     if path == "-":
@@ -137,8 +174,15 @@ def main(argv=None):
     t.add_argument("--precision", default="fp32")
     t.add_argument("--command", required=True)
     t.add_argument("out")
+    q = sub.add_parser("sq", help="SQ counters per dispatch")
+    q.add_argument("out")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--match", required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--precision", default="fp32")
+    q.add_argument("--command", required=True)
     a = ap.parse_args(argv)
-    (cmd_stats if a.cmd == "stats" else cmd_traffic)(a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "sq": cmd_sq}[a.cmd](a)
 
 
 if __name__ == "__main__":
