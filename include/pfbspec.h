@@ -91,7 +91,7 @@ typedef enum { PFBS_MODE_PFB = 0, PFBS_MODE_DIRECT = 1 } pfbs_mode;
  * row pass is where a strong tone's rounding error concentrates (its energy
  * sits in one intermediate row), so MIXED meets the FP32 path's accuracy with
  * the faster 256-point column split at every N.  Batches (pfbs_batch_create)
- * take FP32 plans only. */
+ * take FP32 and MIXED plans. */
 typedef enum {
     PFBS_PREC_FP32 = 0,
     PFBS_PREC_MFMA_FP16 = 1,
@@ -325,20 +325,37 @@ const char *pfbs_last_error(void);
 const char *pfbs_version(void);
 
 /* Batched form: several independent sub-band streams (each with its own N, P,
- * mode, n_int and state) processed by one fixed launch sequence per block,
+ * mode, n_int, precision and state) processed by three launches per block,
  * in the eight-sub-band spirit of the paper's 16 parallel FFTs (Section 4,
- * initialisation) and its remark on per-batch launch overhead (Section 5).
- *   descs: host array of n plan descriptions (all n_pol equal).             */
+ * initialisation) and its remark on per-batch launch overhead (Section 5):
+ * the front phase (every sub-band's single pass or column pass, with its
+ * pre-filter), the row phase (every row pass) and the tail (dump reductions
+ * and tap histories).  Each workgroup runs the same device code as the
+ * sub-band's own plan, so every sub-band's dumps are bitwise those of
+ * pfbs_execute on a plan made from the same description.
+ *   descs: host array of n (1..64) plan descriptions, all with the same
+ *          n_pol, precision FP32 or MIXED, output PRODUCTS, fftshift 0
+ *          (others: PFBS_ERR_UNSUPPORTED).                                  */
 pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int32_t n);
 
 /* One block per sub-band: d_blocks[i] (device) holds n_time_samples[i]
  * samples for sub-band i; d_dumps[i] / caps[i] / n_dumps[i] as in
- * pfbs_execute.  With use_graph != 0 the launch sequence is captured once in
- * a HIP graph and replayed. */
+ * pfbs_execute.  The per-block work tables go to the device with one
+ * asynchronous copy on a stream of the batch, from page-locked staging
+ * memory, while `stream` still runs earlier blocks (a ring of four buffers:
+ * the host waits only for the copy of four executes back).  With
+ * use_graph != 0 the three launches are captured once in a HIP graph (on the
+ * batch's own stream; recaptured when the block sizes change) and replayed
+ * on `stream`, with workgroup counts for the largest work those block sizes
+ * can bring (the surplus workgroups exit at once). */
 pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks,
                                const int64_t *n_time_samples, float *const *d_dumps,
                                const int64_t *caps, int64_t *n_dumps, int32_t use_graph,
                                void *stream);
+
+/* Kernel launches (or graph kernel nodes) of the batch's last execute: at
+ * most 3.  -1 if b is not a live batch. */
+int32_t pfbs_batch_launches(const pfbs_batch *b);
 
 /* Release the batch and the plans it owns.  NULL is accepted. */
 pfbs_status pfbs_batch_destroy(pfbs_batch *b);

@@ -15,17 +15,16 @@ namespace pfbs {
 // column in registers; at the end of the chunk the T columns are summed in
 // column order and written as the chunk's partial sum.
 template <int NPOL, bool PFB, int L, int PREC = 0, int PT = 0>
-__device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid) {
+__device__ __forceinline__ void front_single_body(const FrontArgs &a, int bid, int tid, float *smem) {
     typedef Geom<L, kTilePoints, 5> G;
     typedef typename Sample<NPOL>::word4 W4;
     constexpr int NB = G::TPP * NPOL;      // threads
     constexpr int PTS = kTilePoints / NB;  // pre-filter points per thread (all pols each)
     constexpr int NP = NPOL == 2 ? 4 : 1;  // products
     constexpr int BINS = kTilePoints / NB; // accumulated bins per thread
-    extern __shared__ float smem[];
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
-    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
+    const int pol = tid / G::TPP, lt = tid % G::TPP;
     const long long gid = a.ch.gid0 + bid;
     long long js, je;
     chunk_range(a.ch, gid, js, je);
@@ -221,15 +220,14 @@ __device__ __forceinline__ void cols_tile_item(int ntiles, int bid, int nblk, in
 }
 
 template <int NPOL, bool PFB, int L, int PREC = 0, int PT = 0>
-__device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int nblk) {
+__device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int nblk, int tid, float *smem) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
     constexpr int NB = G::TPP * NPOL;
     constexpr int PTS = G::TP / NB;
-    extern __shared__ float smem[];
     float *sre = smem;
     float *sim = smem + NPOL * G::plane;
-    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
+    const int pol = tid / G::TPP, lt = tid % G::TPP;
     int tile, item;
     cols_tile_item<G::T, NPOL>(a.ntiles, bid, nblk, tile, item);
     // spectra [js, je): the item-th run of ga spectra of the launch's range
@@ -377,15 +375,14 @@ __device__ __forceinline__ void front_cols_body(const FrontArgs &a, int bid, int
 // stores one spectrum, exactly as front_cols_body does (same arithmetic in
 // the same order, so the same bits).
 template <int NPOL, int L, int PT = 0, int PREC = 0>
-__device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid, int nblk) {
+__device__ __forceinline__ void front_cols_pair_body(const FrontArgs &a, int bid, int nblk, int tid, float *smem) {
     typedef Geom<L> G;
     typedef typename Sample<NPOL>::word W;
     typedef typename Sample<NPOL>::word4 W4;
     constexpr int NB = G::TPP * NPOL;   // threads per spectrum
     constexpr int GRP = G::TP / (8 * NB);  // 4-point groups per thread and spectrum
     static_assert(G::T % 4 == 0 && GRP >= 1 && GRP * 8 * NB == G::TP, "pair tile of whole 4-sample groups");
-    extern __shared__ float smem[];
-    const int tid = threadIdx.x, half = tid / NB, t = tid - half * NB;
+    const int half = tid / NB, t = tid - half * NB;
     const int pol = t / G::TPP, lt = t % G::TPP;
     float *sre = smem + half * (2 * NPOL * G::plane);
     float *sim = sre + NPOL * G::plane;
@@ -545,19 +542,21 @@ template <int L, int PREC> struct BackPad {
 // product rounded once to FP32 before it is accumulated); the intermediate
 // stays FP32.  A strong tone's energy sits in one intermediate row, and an
 // FP32 row FFT spreads its rounding over every channel of that row.
-template <int NPOL, int L, int PREC = 0>
-__device__ __forceinline__ void back_body(const BackArgs &a, int bid) {
-    typedef Geom<L, BackTile<L>::TP, BackPad<L, PREC>::PS> G;
+// TP: row-pass tile points (the plan's own launches use BackTile<L>::TP; a
+// batched launch runs every row length of a batch at one tile size, which
+// changes only how rows are grouped into workgroups, not their arithmetic).
+template <int NPOL, int L, int PREC = 0, int TP = BackTile<L>::TP>
+__device__ __forceinline__ void back_body(const BackArgs &a, int bid, int tid, float *smem) {
+    typedef Geom<L, TP, BackPad<L, PREC>::PS> G;
     constexpr bool F64 = PREC == 3;
     typedef std::conditional_t<F64, double, float> T;
     typedef typename Cplx<T>::type C;
     constexpr int NB = G::TPP * NPOL;
     constexpr int NP = NPOL == 2 ? 4 : 1;
     constexpr int BINS = G::TP / NB;
-    extern __shared__ float smem[];
     T *sre = reinterpret_cast<T *>(smem);
     T *sim = sre + NPOL * G::plane;
-    const int tid = threadIdx.x, pol = tid / G::TPP, lt = tid % G::TPP;
+    const int pol = tid / G::TPP, lt = tid % G::TPP;
     const int tile = bid % a.ntiles;
     const long long gid = a.ch.gid0 + bid / a.ntiles;
     long long js, je;

@@ -401,14 +401,11 @@ hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long 
 
 const void *batch_tail_fn() { return reinterpret_cast<const void *>(&k_batch_tail); }
 
-hipError_t init_batch(int lds_limit);
-
 hipError_t kernels_init() {
     const int lim = 96 * 1024;  // largest workgroup LDS is ~74 KB
     hipError_t e = init_single(lim);
     hipError_t e2 = init_fourstep(lim);
-    hipError_t e3 = init_batch(lim);
-    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);
+    return e != hipSuccess ? e : e2;
 }
 
 }  // namespace pfbs

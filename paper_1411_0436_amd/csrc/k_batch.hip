@@ -1,11 +1,13 @@
-// Batched launches for several sub-bands.  Entries of one kernel variant
-// (kind, polarisations, filter, sub-FFT length) share one launch; each
+// Batched launches for several sub-bands: one launch per phase of a block.
+// The paper's eight-sub-band mode runs its 16 FFTs in parallel (Section 4)
+// and attributes small-N slowness to per-batch launch overhead (Section 5).
+// Here a block of every sub-band is three launches: the front phase (single
+// passes and column passes of all sub-bands), the row phase (all row passes)
+// and the tail (dump reductions and tap histories, k_aux.hip).  Each
 // workgroup finds its sub-band entry from its block id and runs the same
-// device body as that sub-band's own kernel, at that kernel's own register
-// budget.  The paper's eight-sub-band mode runs its 16 FFTs in parallel
-// (Section 4) and attributes small-N slowness to per-batch launch overhead
-// (Section 5); here a block of all sub-bands is a handful of launches, which
-// can be replayed from one HIP graph.
+// device body as that sub-band's own kernel, so a batch gives the same bits
+// as separate plans; the sub-bands' workgroups share the machine instead of
+// queueing behind one another's partly filled launches.
 #include "fft_bodies.h"
 
 namespace pfbs {
@@ -17,108 +19,132 @@ __device__ __forceinline__ int find_entry(const E *t, int n, int bid) {
     return e;
 }
 
-template <int NPOL, bool PFB, int L, int PT = 0>
-__global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_multi_single(const BatchFrontEntry *__restrict__ t, int n) {
+// LDS floats of one one-spectrum front workgroup (the host's front_lds_bytes).
+template <int NPOL, int L>
+constexpr int front_lds_floats() { return 2 * NPOL * (kTilePoints / L) * lds_pitch(L); }
+
+// Front phase.  A workgroup is twice the threads of a one-spectrum front
+// kernel: a two-spectra column entry uses it whole, exactly as its own
+// kernel; single-pass and one-spectrum column entries run two of their
+// workgroups in it, one per half (whole waves), each half with its own LDS.
+// Physical block b of an entry (entries start on multiples of 8, so b mod 8
+// is the XCD) holds virtual blocks 16*(b/8) + 8*half + b mod 8: the XCD
+// mapping of the column pass sees the same XCD as a plan's own launch, and
+// the two halves of a CU take adjacent items (consecutive spectra of one
+// column tile, which share frames in its cache).  The halves synchronise
+// with workgroup barriers that both take part in; a half whose work ends
+// first exits, and a barrier then waits only for the waves still running.
+template <int NPOL>
+__global__ __launch_bounds__(2 * kTilePoints / 16 * NPOL, 4) void k_batch_front(const BatchFrontEntry *__restrict__ t,
+                                                                           int n) {
+    extern __shared__ float smem[];
     if (n <= 0) return;
     const int e = find_entry(t, n, blockIdx.x);
-    const int vb = blockIdx.x - t[e].wg0;
-    if (vb < 0 || vb >= t[e].wgn) return;
-    // a private copy: the body's global stores cannot alias it, so its fields
-    // stay in registers instead of being reloaded after every store
+    const int lb = blockIdx.x - t[e].wg0;
+    if (lb < 0 || lb >= t[e].wgn) return;
+    // a private copy: the body's global stores cannot alias it
     FrontArgs a = t[e].a;
     globalise(a);
-    front_single_body<NPOL, PFB, L, 0, PT>(a, vb);
+    const int kind = t[e].kind, L = t[e].L, pt = t[e].pt, items = t[e].items;
+    const bool pfb = t[e].pfb != 0;
+    if (kind == 2) {
+#define PFBS_BF_PAIR(LL)                                                                                  \
+    if (L == LL) {                                                                                        \
+        if (pt == 4) front_cols_pair_body<NPOL, LL, 4, 0>(a, lb, items, threadIdx.x, smem);               \
+        else if (pt == 8) front_cols_pair_body<NPOL, LL, 8, 0>(a, lb, items, threadIdx.x, smem);          \
+        else front_cols_pair_body<NPOL, LL, 0, 0>(a, lb, items, threadIdx.x, smem);                       \
+        return;                                                                                           \
+    }
+        PFBS_BF_PAIR(64) PFBS_BF_PAIR(128) PFBS_BF_PAIR(256)
+#undef PFBS_BF_PAIR
+        return;
+    }
+    constexpr int HALF = kTilePoints / 16 * NPOL;
+    // wave-uniform: whole waves make up each half
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >= HALF ? 1 : 0;
+    const int vb = ((lb >> 3) << 4) + (half << 3) + (lb & 7);
+    if (vb >= items) return;
+    const int tid = (int)threadIdx.x - half * HALF;
+    if (kind == 0) {
+#define PFBS_BF_SINGLE(LL)                                                                                \
+    if (L == LL) {                                                                                        \
+        float *lds = smem + half * front_lds_floats<NPOL, LL>();                                          \
+        if (pfb) front_single_body<NPOL, true, LL, 0, 0>(a, vb, tid, lds);                                \
+        else front_single_body<NPOL, false, LL, 0, 0>(a, vb, tid, lds);                                   \
+        return;                                                                                           \
+    }
+        PFBS_BF_SINGLE(16) PFBS_BF_SINGLE(32) PFBS_BF_SINGLE(64) PFBS_BF_SINGLE(128) PFBS_BF_SINGLE(256)
+        PFBS_BF_SINGLE(512) PFBS_BF_SINGLE(1024) PFBS_BF_SINGLE(2048) PFBS_BF_SINGLE(4096)
+#undef PFBS_BF_SINGLE
+        return;
+    }
+#define PFBS_BF_COLS(LL)                                                                                  \
+    if (L == LL) {                                                                                        \
+        float *lds = smem + half * front_lds_floats<NPOL, LL>();                                          \
+        if (!pfb) front_cols_body<NPOL, false, LL, 0, 0>(a, vb, items, tid, lds);                         \
+        else if (pt == 4) front_cols_body<NPOL, true, LL, 0, 4>(a, vb, items, tid, lds);                  \
+        else if (pt == 8) front_cols_body<NPOL, true, LL, 0, 8>(a, vb, items, tid, lds);                  \
+        else front_cols_body<NPOL, true, LL, 0, 0>(a, vb, items, tid, lds);                               \
+        return;                                                                                           \
+    }
+    PFBS_BF_COLS(64) PFBS_BF_COLS(128) PFBS_BF_COLS(256) PFBS_BF_COLS(512)
+#undef PFBS_BF_COLS
 }
 
-template <int NPOL, bool PFB, int L, int PT = 0>
-__global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_multi_cols(const BatchFrontEntry *__restrict__ t, int n) {
+// Row phase: every row length and row arithmetic of a batch at one tile of
+// TP points per polarisation (TP / L rows per workgroup step).
+template <int NPOL, int TP>
+__global__ __launch_bounds__(TP / 16 * NPOL) void k_batch_back(const BatchBackEntry *__restrict__ t, int n) {
+    extern __shared__ float smem[];
     if (n <= 0) return;
     const int e = find_entry(t, n, blockIdx.x);
-    const int vb = blockIdx.x - t[e].wg0, wgn = t[e].wgn;
-    if (vb < 0 || vb >= wgn) return;
-    FrontArgs a = t[e].a;
-    globalise(a);
-    front_cols_body<NPOL, PFB, L, 0, PT>(a, vb, wgn);
-}
-
-template <int NPOL, int L, int PREC = 0>
-__global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_multi_back(const BatchBackEntry *__restrict__ t, int n) {
-    if (n <= 0) return;
-    const int e = find_entry(t, n, blockIdx.x);
-    const int vb = blockIdx.x - t[e].wg0;
-    if (vb < 0 || vb >= t[e].wgn) return;
+    const int lb = blockIdx.x - t[e].wg0;
+    if (lb < 0 || lb >= t[e].wgn) return;
     BackArgs a = t[e].a;
     globalise(a);
-    back_body<NPOL, L, PREC>(a, vb);
+    const int L = t[e].L, prec = t[e].prec;
+#define PFBS_BB(LL)                                                                                       \
+    if constexpr (LL <= TP) {                                                                             \
+        if (L == LL) {                                                                                    \
+            if (prec == 3) back_body<NPOL, LL, 3, TP>(a, lb, threadIdx.x, smem);                          \
+            else if (prec == 2) back_body<NPOL, LL, 2, TP>(a, lb, threadIdx.x, smem);                     \
+            else back_body<NPOL, LL, 0, TP>(a, lb, threadIdx.x, smem);                                    \
+            return;                                                                                       \
+        }                                                                                                 \
+    }
+    PFBS_BB(32) PFBS_BB(64) PFBS_BB(128) PFBS_BB(256) PFBS_BB(512) PFBS_BB(1024) PFBS_BB(2048) PFBS_BB(4096)
+#undef PFBS_BB
 }
 
-#define PFBS_M_SINGLE(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-#define PFBS_M_COLS(X) X(64) X(128) X(256) X(512)
-#define PFBS_M_BACK(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-
-// pt: compile-time tap count of the variant (4 or 8), 0 = from the entry.
-const void *multi_front_fn(int npol, int kind, int pfb, int L, int pt) {
-#define PFBS_F(KERN, LL)                                                                       \
-    if (L == LL) {                                                                             \
-        if (npol == 2) {                                                                       \
-            if (!pfb) return reinterpret_cast<const void *>(&KERN<2, false, LL>);              \
-            if (pt == 4) return reinterpret_cast<const void *>(&KERN<2, true, LL, 4>);         \
-            if (pt == 8) return reinterpret_cast<const void *>(&KERN<2, true, LL, 8>);         \
-            return reinterpret_cast<const void *>(&KERN<2, true, LL>);                         \
-        }                                                                                      \
-        if (!pfb) return reinterpret_cast<const void *>(&KERN<1, false, LL>);                  \
-        if (pt == 4) return reinterpret_cast<const void *>(&KERN<1, true, LL, 4>);             \
-        if (pt == 8) return reinterpret_cast<const void *>(&KERN<1, true, LL, 8>);             \
-        return reinterpret_cast<const void *>(&KERN<1, true, LL>);                             \
-    }
-    if (kind == 0) {
-#define PFBS_S(LL) PFBS_F(k_multi_single, LL)
-        PFBS_M_SINGLE(PFBS_S)
-#undef PFBS_S
-    } else {
-#define PFBS_C(LL) PFBS_F(k_multi_cols, LL)
-        PFBS_M_COLS(PFBS_C)
-#undef PFBS_C
-    }
-#undef PFBS_F
-    return nullptr;
+const void *batch_front_fn(int npol) {
+    return npol == 2 ? reinterpret_cast<const void *>(&k_batch_front<2>)
+                     : reinterpret_cast<const void *>(&k_batch_front<1>);
 }
 
-// prec: 0 FP32, 3 FP64 row pass.
-const void *multi_back_fn(int npol, int L, int prec) {
-#define PFBS_B(LL)                                                                                   \
-    if (L == LL) {                                                                                   \
-        if (prec == 3) return npol == 2 ? reinterpret_cast<const void *>(&k_multi_back<2, LL, 3>)    \
-                                        : reinterpret_cast<const void *>(&k_multi_back<1, LL, 3>);   \
-        if (prec == 0) return npol == 2 ? reinterpret_cast<const void *>(&k_multi_back<2, LL>)       \
-                                        : reinterpret_cast<const void *>(&k_multi_back<1, LL>);      \
+const void *batch_back_fn(int npol, int tp) {
+    switch (tp) {
+    case 1024: return npol == 2 ? reinterpret_cast<const void *>(&k_batch_back<2, 1024>)
+                                : reinterpret_cast<const void *>(&k_batch_back<1, 1024>);
+    case 2048: return npol == 2 ? reinterpret_cast<const void *>(&k_batch_back<2, 2048>)
+                                : reinterpret_cast<const void *>(&k_batch_back<1, 2048>);
+    case 4096: return npol == 2 ? reinterpret_cast<const void *>(&k_batch_back<2, 4096>)
+                                : reinterpret_cast<const void *>(&k_batch_back<1, 4096>);
+    default: return nullptr;
     }
-    PFBS_M_BACK(PFBS_B)
-#undef PFBS_B
-    return nullptr;
 }
 
-hipError_t init_batch(int lds_limit) {
-    hipError_t e = hipSuccess;
-    for (int npol = 1; npol <= 2; ++npol)
-        for (int pfb = 0; pfb <= 1; ++pfb)
-            for (int kind = 0; kind <= 1; ++kind)
-                for (int L = 16; L <= 4096; L *= 2)
-                    for (int pt : {0, 4, 8}) {
-                        const void *f = multi_front_fn(npol, kind, pfb, L, pt);
-                        if (!f) continue;
-                        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
-                        if (r != hipSuccess) e = r;
-                    }
-    for (int npol = 1; npol <= 2; ++npol)
-        for (int L = 32; L <= 4096; L *= 2)
-            for (int prec : {0, 3}) {
-                const void *f = multi_back_fn(npol, L, prec);
-                if (!f) continue;
-                hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
-                if (r != hipSuccess) e = r;
-            }
-    return e;
+bool init_batch(int lds_limit) {
+    bool ok = true;
+    for (int npol = 1; npol <= 2; ++npol) {
+        if (hipFuncSetAttribute(batch_front_fn(npol), hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) !=
+            hipSuccess)
+            ok = false;
+        for (int tp : {1024, 2048, 4096})
+            if (hipFuncSetAttribute(batch_back_fn(npol, tp), hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) !=
+                hipSuccess)
+                ok = false;
+    }
+    return ok;
 }
 
 }  // namespace pfbs

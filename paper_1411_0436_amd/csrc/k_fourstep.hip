@@ -19,17 +19,20 @@ template <int L, int PREC> struct ColsMinWaves {
 // unrolled and software-pipelined), 0 = taken from the arguments.
 template <int NPOL, bool PFB, int L, int PREC, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL, (ColsMinWaves<L, PREC>::value)) void k_front_cols(FrontArgs a) {
-    front_cols_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x, gridDim.x);
+    extern __shared__ float smem[];
+    front_cols_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x, gridDim.x, threadIdx.x, smem);
 }
 
 template <int NPOL, int L, int PT = 0, int PREC = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL * 2) void k_front_cols_pair(FrontArgs a) {
-    front_cols_pair_body<NPOL, L, PT, PREC>(a, blockIdx.x, gridDim.x);
+    extern __shared__ float smem[];
+    front_cols_pair_body<NPOL, L, PT, PREC>(a, blockIdx.x, gridDim.x, threadIdx.x, smem);
 }
 
 template <int NPOL, int L, int PREC>
 __global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a) {
-    back_body<NPOL, L, PREC>(a, blockIdx.x);
+    extern __shared__ float smem[];
+    back_body<NPOL, L, PREC>(a, blockIdx.x, threadIdx.x, smem);
 }
 
 #define PFBS_COLS_CASES(X) X(64) X(128) X(256) X(512)

@@ -8,7 +8,8 @@ namespace pfbs {
 // unrolled and software-pipelined), 0 = taken from the arguments.
 template <int NPOL, bool PFB, int L, int PREC, int PT = 0>
 __global__ __launch_bounds__(kTilePoints / 16 * NPOL) void k_front_single(FrontArgs a) {
-    front_single_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x);
+    extern __shared__ float smem[];
+    front_single_body<NPOL, PFB, L, PREC, PT>(a, blockIdx.x, threadIdx.x, smem);
 }
 
 #define PFBS_SINGLE_CASES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)

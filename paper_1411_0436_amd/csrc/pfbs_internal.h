@@ -112,15 +112,18 @@ struct ReduceArgs {
 constexpr int kMaxBatch = 64;
 
 struct BatchFrontEntry {
-    int kind;        // 0 = single pass, 1 = column pass
+    int kind;        // 0 = single pass, 1 = column pass, 2 = two-spectra column pass
     int pfb;
     int L;
-    int wg0, wgn;    // the entry's virtual block ids are [wg0, wg0 + wgn)
+    int pt;          // compile-time tap count of the body (4, 8; 0 = from the arguments)
+    int wg0, wgn;    // the entry's workgroups are [wg0, wg0 + wgn) of the launch
+    int items;       // the body's block count (kinds 0 and 1: two per workgroup)
     FrontArgs a;
 };
 
 struct BatchBackEntry {
     int L;
+    int prec;        // row arithmetic: 0 FP32, 2 split FP16 on the matrix cores, 3 FP64
     int wg0, wgn;
     BackArgs a;
 };
@@ -136,12 +139,13 @@ struct BatchTailEntry {
     int H;
 };
 
-// Kernels of the batched launches (see k_batch.hip): one per variant.
-const void *multi_front_fn(int npol, int kind, int pfb, int L, int pt);
+// Kernels of the batched launches (k_batch.hip, k_aux.hip): the front phase,
+// the row phase at tile size tp (1024, 2048 or 4096 points), the tail.
+const void *batch_front_fn(int npol);
+const void *batch_back_fn(int npol, int tp);
 // Compile-time tap count of the pre-filter kernels for P taps (0: taken from
 // the arguments at run time; also 0 without the filter or when not unrolled).
 constexpr int tap_variant(bool pfb, int P, bool unroll) { return unroll && pfb && (P == 4 || P == 8) ? P : 0; }
-const void *multi_back_fn(int npol, int L, int prec);
 const void *batch_tail_fn();
 
 }  // namespace pfbs
@@ -199,6 +203,7 @@ hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long 
                             int npol, bool pfb, long long j_lo, long long j_hi, hipStream_t s);
 hipError_t kernels_init();   // raise LDS limits once per process/device
 bool init_fourstep_pair(int lds_limit);  // LDS limit of the two-spectra column kernels; false if refused
+bool init_batch(int lds_limit);          // LDS limit of the batched phase kernels; false if refused
 size_t front_lds_bytes(const Geo &g, int npol);
 size_t back_lds_bytes(const Geo &g, int npol, int prec);
 

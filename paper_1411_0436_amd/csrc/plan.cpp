@@ -95,6 +95,7 @@ void *g_scratch_ptr[64];
 // Column pass on two spectra per workgroup step: its LDS (twice the one-spectrum
 // kernel's, up to 140 KB) is available on the device.
 bool g_pair_ok[64];
+bool g_batch_ok[64];
 constexpr int kPairLds = 160 * 1024;
 
 }  // namespace
@@ -156,28 +157,32 @@ struct pfbs_batch {
     uint32_t magic;
     std::vector<pfbs_plan *> plans;
     int npol;
-    // kernel variants present (fixed by the sub-band shapes): one launch each
-    struct FVar { int kind, pfb, L, pt; std::vector<int> plans; };
-    struct BVar { int fvar, L, prec; std::vector<int> plans; };   // row passes of one column-pass group
-    std::vector<FVar> fvars;
-    std::vector<BVar> bvars;
-    // entry tables: device copy read by the kernels, two pinned staging copies
+    int tpb;        // row-phase tile points per polarisation (1024, 2048 or 4096)
+    int launches;   // kernel launches made by the last execute
+    // entry tables, a ring of kTabRing buffers: buffer k is filled on the
+    // host, copied to the device on the batch's copy stream while the
+    // caller's stream still runs earlier blocks, and read by the kernels of
+    // the execute that filled it.  The host waits only for the upload of
+    // kTabRing executes back, so it can stay that many blocks ahead.
     struct Tables {
         BatchFrontEntry front[kMaxBatch];
         BatchBackEntry back[kMaxBatch];
         BatchTailEntry tail[2 * kMaxBatch];
     };
-    Tables *d_tab;
-    Tables *h_tab[2];
-    hipEvent_t staged[2];
+    static constexpr int kTabRing = 4;
+    Tables *d_tab[kTabRing];
+    Tables *h_tab[kTabRing];
+    hipEvent_t copied[kTabRing];   // upload of buffer k done (its host copy is free)
+    hipEvent_t done[kTabRing];     // kernels that read device buffer k done
     int stage;
-    // HIP graph of the launch sequence with upper-bound grids, captured on
-    // first use for one set of block sizes
+    hipStream_t cstream;    // table copies
+    // HIP graphs of the three launches (one per table buffer) with upper-bound
+    // grids, captured on a stream of their own on first use for one set of
+    // block sizes, replayed on the caller's stream
     hipStream_t gstream;
-    hipEvent_t ev_in, ev_out;
-    hipGraph_t graph;
-    hipGraphExec_t gexec;
-    std::vector<int64_t> gsizes;
+    hipGraph_t graph[kTabRing];
+    hipGraphExec_t gexec[kTabRing];
+    std::vector<int64_t> gsizes[kTabRing];
 };
 
 namespace {
@@ -391,6 +396,7 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
             if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
             g_scratch_ptr[dev] = sp;
             g_pair_ok[dev] = init_fourstep_pair(kPairLds);
+            g_batch_ok[dev] = init_batch(kPairLds);
             g_init_done[dev] = true;
         }
     }
@@ -741,8 +747,7 @@ pfbs_status prepare(pfbs_plan *p, const void *d_block, int64_t n, float *d_dumps
             g.fa.ga = p->ga_force > 0 ? p->ga_force : 1;
             g.fa.znt = p->znt;
             g.ba.znt = p->znt;
-            // batches (one_group) run the one-spectrum column kernel
-            g.fa.pair = p->pair && !one_group;
+            g.fa.pair = p->pair;
             const int64_t run = (int64_t)g.fa.ga * (g.fa.pair ? 2 : 1);
             // items padded to a multiple of 8 for the XCD mapping (the
             // padding items find their spectra past the range and do nothing)
@@ -984,16 +989,16 @@ namespace {
 void batch_free(pfbs_batch *b) {
     for (pfbs_plan *p : b->plans) pfbs_plan_destroy(p);
     b->plans.clear();
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->gstream) (void)hipStreamDestroy(b->gstream);
-    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
-    for (int k = 0; k < 2; ++k) {
-        if (b->staged[k]) (void)hipEventDestroy(b->staged[k]);
+    for (int k = 0; k < pfbs_batch::kTabRing; ++k) {
+        if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+        if (b->done[k]) (void)hipEventDestroy(b->done[k]);
         if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+        if (b->d_tab[k]) (void)hipFree(b->d_tab[k]);
     }
-    if (b->d_tab) (void)hipFree(b->d_tab);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    if (b->cstream) (void)hipStreamDestroy(b->cstream);
 }
 
 // One kernel launch of a batched block.
@@ -1015,6 +1020,16 @@ int reduce_gx(const pfbs_plan *p) {
 int hist_wg(const pfbs_plan *p) {
     return (int)std::min<int64_t>(1024, ((int64_t)(p->P - 1) * (p->frame_bytes / 16) + 255) / 256);
 }
+// Front-phase workgroups for `items` body blocks: two per workgroup (one per
+// half) in groups of 8 workgroups, or one each for the two-spectra kernel.
+int front_wg(int kind, int64_t items) {
+    return kind == 2 ? (int)((items + 7) / 8 * 8) : (int)((items + 15) / 16 * 8);
+}
+// Row-phase tiles of a plan at the batch's tile size.
+int batch_ntiles_b(const pfbs_plan *p, int tpb) { return (int)(p->N2 / (tpb / p->N1)); }
+size_t batch_back_lds(const pfbs_plan *p, int tpb) {
+    return back_lds_bytes(make_geo((int)p->N1, tpb), p->npol, p->prec_back);
+}
 
 }  // namespace
 
@@ -1028,8 +1043,8 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
         pfbs_status st = validate_desc(&descs[i]);
         if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
         if (descs[i].n_pol != descs[0].n_pol) return fail(PFBS_ERR_INVALID, "all sub-bands need the same n_pol");
-        if (descs[i].precision != PFBS_PREC_FP32)
-            return fail(PFBS_ERR_UNSUPPORTED, "sub-band %d: batched launches run the FP32 path", i);
+        if (descs[i].precision != PFBS_PREC_FP32 && descs[i].precision != PFBS_PREC_MIXED)
+            return fail(PFBS_ERR_UNSUPPORTED, "sub-band %d: batched launches run the FP32 and MIXED paths", i);
         if (descs[i].output != PFBS_OUT_PRODUCTS || descs[i].fftshift != 0)
             return fail(PFBS_ERR_UNSUPPORTED, "sub-band %d: batched launches write the products in natural order", i);
     }
@@ -1037,6 +1052,7 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
     if (!b) return fail(PFBS_ERR_NOMEM, "host allocation");
     b->magic = kMagic;
     b->npol = descs[0].n_pol;
+    b->tpb = 1024;
     pfbs_status st = PFBS_OK;
     for (int i = 0; i < n && st == PFBS_OK; ++i) {
         pfbs_plan *p = nullptr;
@@ -1047,35 +1063,32 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
             break;
         }
         b->plans.push_back(p);
-        const int kind = p->fourstep ? 1 : 0, pfb = p->pfb ? 1 : 0, L = (int)p->gA.L;
-        const int pt = tap_variant(p->pfb, p->P, p->tap_unroll == 1);
-        auto same = [&](const pfbs_batch::FVar &v) { return v.kind == kind && v.pfb == pfb && v.L == L && v.pt == pt; };
-        auto fv = std::find_if(b->fvars.begin(), b->fvars.end(), same);
-        if (fv == b->fvars.end()) b->fvars.push_back({kind, pfb, L, pt, {i}});
-        else fv->plans.push_back(i);
-        if (p->fourstep) {
-            const int fi = (int)(std::find_if(b->fvars.begin(), b->fvars.end(), same) - b->fvars.begin());
-            auto bv = std::find_if(b->bvars.begin(), b->bvars.end(), [&](const pfbs_batch::BVar &v) {
-                return v.fvar == fi && v.L == (int)p->N1 && v.prec == p->prec_back;
-            });
-            if (bv == b->bvars.end()) b->bvars.push_back({fi, (int)p->N1, p->prec_back, {i}});
-            else bv->plans.push_back(i);
+        if (p->fourstep) b->tpb = std::max(b->tpb, back_tile((int)p->N1));
+    }
+    if (st == PFBS_OK && !g_batch_ok[b->plans[0]->device])
+        st = fail(PFBS_ERR_UNSUPPORTED, "the device refused the LDS size of the batched kernels");
+    if (st == PFBS_OK) {
+        // LDS of the two phase workgroups
+        size_t lf = 0, lb = 0;
+        for (pfbs_plan *p : b->plans) {
+            lf = std::max(lf, 2 * front_lds_bytes(p->gA, p->npol));
+            if (p->fourstep) lb = std::max(lb, batch_back_lds(p, b->tpb));
         }
+        if (lf > (size_t)kPairLds || lb > (size_t)kPairLds)
+            st = fail(PFBS_ERR_UNSUPPORTED, "batched launches need %zu / %zu bytes of LDS (limit %d)", lf, lb,
+                      kPairLds);
     }
     hipError_t e = hipSuccess;
-    if (st == PFBS_OK) {
-        if ((e = hipMalloc((void **)&b->d_tab, sizeof(pfbs_batch::Tables))) == hipSuccess &&
-            (e = hipHostMalloc((void **)&b->h_tab[0], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
-            (e = hipHostMalloc((void **)&b->h_tab[1], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
-            (e = hipEventCreateWithFlags(&b->staged[0], hipEventDisableTiming)) == hipSuccess &&
-            (e = hipEventCreateWithFlags(&b->staged[1], hipEventDisableTiming)) == hipSuccess &&
-            (e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) == hipSuccess &&
-            (e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) == hipSuccess) {
-            // default-priority stream for graph replays, joined to the caller's by events
-            e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
-        }
-        if (e != hipSuccess) st = hip_fail(nullptr, e, "batch resources");
+    for (int k = 0; k < pfbs_batch::kTabRing && st == PFBS_OK && e == hipSuccess; ++k) {
+        if ((e = hipMalloc((void **)&b->d_tab[k], sizeof(pfbs_batch::Tables))) == hipSuccess &&
+            (e = hipHostMalloc((void **)&b->h_tab[k], sizeof(pfbs_batch::Tables), hipHostMallocDefault)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming)) == hipSuccess)
+            e = hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming);
     }
+    // default-priority streams: table copies, and the one graphs are captured on
+    if (st == PFBS_OK && e == hipSuccess && (e = hipStreamCreateWithFlags(&b->cstream, hipStreamNonBlocking)) == hipSuccess)
+        e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+    if (st == PFBS_OK && e != hipSuccess) st = hip_fail(nullptr, e, "batch resources");
     if (st != PFBS_OK) {
         batch_free(b);
         delete b;
@@ -1097,97 +1110,108 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
         if (st != PFBS_OK) return fail(st, "sub-band %d: %s", i, g_err.c_str());
     }
     pfbs_plan *p0 = b->plans[0];
+    // ---- entry tables (buffer k; the host copy is free once its last upload is done)
+    const int k = b->stage;
+    hipError_t e = hipEventSynchronize(b->copied[k]);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "batch staging");
     // a graph replays fixed grids: recapture when the block sizes change
     const std::vector<int64_t> sizes(n_samples, n_samples + n);
-    if (use_graph && b->gexec && sizes != b->gsizes) {
-        (void)hipGraphExecDestroy(b->gexec);
-        (void)hipGraphDestroy(b->graph);
-        b->gexec = nullptr;
-        b->graph = nullptr;
+    if (use_graph && b->gexec[k] && sizes != b->gsizes[k]) {
+        (void)hipGraphExecDestroy(b->gexec[k]);
+        (void)hipGraphDestroy(b->graph[k]);
+        b->gexec[k] = nullptr;
+        b->graph[k] = nullptr;
     }
-    // ---- entry tables (host staging buffer k; wait until its last upload is done)
-    const int k = b->stage;
-    hipError_t e = hipEventSynchronize(b->staged[k]);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "batch staging");
     pfbs_batch::Tables &T = *b->h_tab[k];
-    char *dbase = reinterpret_cast<char *>(b->d_tab);
+    char *dbase = reinterpret_cast<char *>(b->d_tab[k]);
     const BatchFrontEntry *d_front =
         reinterpret_cast<const BatchFrontEntry *>(dbase + offsetof(pfbs_batch::Tables, front));
     const BatchBackEntry *d_back =
         reinterpret_cast<const BatchBackEntry *>(dbase + offsetof(pfbs_batch::Tables, back));
     const BatchTailEntry *d_tail =
         reinterpret_cast<const BatchTailEntry *>(dbase + offsetof(pfbs_batch::Tables, tail));
-    std::vector<BLaunch> L, LF, LB;
-    int nf = 0;
-    for (const pfbs_batch::FVar &v : b->fvars) {  // one launch per column/single-pass variant
-        const int first = nf;
-        int wg = 0, wg_max = 0;
-        size_t lds = 0;
-        for (int i : v.plans) {
-            pfbs_plan *p = b->plans[i];
-            const int64_t F = n_samples[i] / p->N;
-            BatchFrontEntry &E = T.front[nf++];
-            memset(&E, 0, sizeof E);
-            E.kind = v.kind;
-            E.pfb = v.pfb;
-            E.L = v.L;
-            E.wg0 = wg;
+    std::vector<BLaunch> L;
+
+    // ---- front phase: every sub-band's single pass or column pass.  Entries
+    // with the longest work per workgroup first (single passes walk a whole
+    // chunk of spectra), so that they start while the rest fill the machine.
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto kind_of = [&](int i) { return !b->plans[i]->fourstep ? 0 : (w[i].any && w[i].groups[0].fa.pair ? 2 : 1); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int kx = kind_of(x), ky = kind_of(y);
+        const int rx = kx == 0 ? 0 : (kx == 2 ? 1 : 2), ry = ky == 0 ? 0 : (ky == 2 ? 1 : 2);
+        if (rx != ry) return rx < ry;
+        return b->plans[x]->N > b->plans[y]->N;
+    });
+    int nf = 0, wf = 0, wf_max = 0;
+    size_t lds_f = 0;
+    for (int i : order) {
+        pfbs_plan *p = b->plans[i];
+        const int64_t F = n_samples[i] / p->N;
+        const int kind = kind_of(i);
+        BatchFrontEntry &E = T.front[nf++];
+        memset(&E, 0, sizeof E);
+        E.kind = kind;
+        E.pfb = p->pfb ? 1 : 0;
+        E.L = (int)p->gA.L;
+        E.wg0 = wf;
+        int64_t items_max;
+        const int64_t ga = std::max(1, p->ga_force);
+        if (kind == 0) {
             if (w[i].any) {
-                if (v.kind == 0) {
-                    E.a = w[i].single;
-                    E.wgn = w[i].single_chunks;
-                } else {
-                    E.a = w[i].groups[0].fa;
-                    E.wgn = w[i].groups[0].na * p->ntilesA;
-                }
+                E.a = w[i].single;
+                E.items = w[i].single_chunks;
             }
-            // entries start on a multiple of 8 workgroups: workgroups are dealt
-            // to the 8 XCDs round-robin and the column pass maps its tiles to
-            // XCDs by block id
-            wg += (E.wgn + 7) & ~7;
-            // upper bound for the captured graph: the column pass's item count
-            // is padded to a multiple of 8 (as in prepare)
-            const int64_t ga = std::max(1, p->ga_force);
-            wg_max += (int)((v.kind == 0 ? max_chunks(p, F) : p->ntilesA * (((F + ga - 1) / ga + 7) / 8 * 8)) + 7) & ~7;
-            lds = std::max(lds, front_lds_bytes(p->gA, p->npol));
-        }
-        LF.push_back({multi_front_fn(b->npol, v.kind, v.pfb, v.L, v.pt), use_graph ? wg_max : wg,
-                      kTilePoints / 16 * b->npol, lds, d_front + first, nf - first});
-    }
-    int nbk = 0;
-    for (const pfbs_batch::BVar &v : b->bvars) {  // one launch per row-pass variant
-        const int first = nbk;
-        int wg = 0, wg_max = 0;
-        size_t lds = 0;
-        int threads = 0;
-        for (int i : v.plans) {
-            pfbs_plan *p = b->plans[i];
-            const int64_t F = n_samples[i] / p->N;
-            BatchBackEntry &E = T.back[nbk++];
-            memset(&E, 0, sizeof E);
-            E.L = v.L;
-            E.wg0 = wg;
+            items_max = max_chunks(p, F);
+        } else {
             if (w[i].any) {
-                E.a = w[i].groups[0].ba;
-                E.wgn = w[i].groups[0].nc * p->ntilesB;
+                E.a = w[i].groups[0].fa;
+                E.items = w[i].groups[0].na * p->ntilesA;
             }
-            wg += E.wgn;
-            wg_max += (int)(p->ntilesB * max_chunks(p, F));
-            lds = std::max(lds, back_lds_bytes(p->gB, p->npol, p->prec_back));
-            threads = back_tile(p->N1) / 16 * p->npol;
+            const int64_t run = ga * (kind == 2 ? 2 : 1);
+            items_max = p->ntilesA * (((F + run - 1) / run + 7) / 8 * 8);
         }
-        LB.push_back({multi_back_fn(b->npol, v.L, v.prec), use_graph ? wg_max : wg, threads, lds, d_back + first,
-                      nbk - first});
+        E.pt = w[i].any ? E.a.pt : 0;
+        E.wgn = w[i].any ? front_wg(kind, E.items) : 0;
+        wf += E.wgn;
+        wf_max += front_wg(kind, items_max);
+        lds_f = std::max(lds_f, 2 * front_lds_bytes(p->gA, p->npol));
     }
-    // each column-pass group is followed by its own row passes, so that their
-    // intermediate is read back while it is still in the Infinity Cache
-    for (size_t fi = 0; fi < LF.size(); ++fi) {
-        L.push_back(LF[fi]);
-        for (size_t bi = 0; bi < b->bvars.size(); ++bi)
-            if (b->bvars[bi].fvar == (int)fi) L.push_back(LB[bi]);
+    if (wf > 0 || use_graph)
+        L.push_back({batch_front_fn(b->npol), use_graph ? wf_max : wf, 2 * kTilePoints / 16 * b->npol, lds_f,
+                     d_front, nf});
+
+    // ---- row phase: every four-step sub-band's row pass at one tile size
+    int nbk = 0, wb = 0, wb_max = 0;
+    size_t lds_b = 0;
+    for (int i : order) {
+        pfbs_plan *p = b->plans[i];
+        if (!p->fourstep) continue;
+        const int64_t F = n_samples[i] / p->N;
+        const int ntb = batch_ntiles_b(p, b->tpb);
+        BatchBackEntry &E = T.back[nbk++];
+        memset(&E, 0, sizeof E);
+        E.L = (int)p->N1;
+        E.prec = p->prec_back;
+        E.wg0 = wb;
+        if (w[i].any) {
+            E.a = w[i].groups[0].ba;
+            E.a.ntiles = ntb;
+            E.a.g.T = b->tpb / (int)p->N1;
+            E.wgn = w[i].groups[0].nc * ntb;
+        }
+        wb += E.wgn;
+        wb_max += (int)(ntb * max_chunks(p, F));
+        lds_b = std::max(lds_b, batch_back_lds(p, b->tpb));
     }
+    if (nbk > 0 && (wb > 0 || use_graph))
+        L.push_back({batch_back_fn(b->npol, b->tpb), use_graph ? wb_max : wb, b->tpb / 16 * b->npol, lds_b, d_back,
+                     nbk});
+
+    // ---- tail: dump reductions and history copies
     int ntl = 0, wt = 0, wt_max = 0;
-    for (int i = 0; i < n; ++i) {  // dump reductions and history copies: one launch
+    for (int i = 0; i < n; ++i) {
         pfbs_plan *p = b->plans[i];
         const int64_t F = n_samples[i] / p->N;
         BatchTailEntry &R = T.tail[ntl++];
@@ -1217,26 +1241,28 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             wt_max += H.wgn;
         }
     }
-    L.push_back({batch_tail_fn(), use_graph ? wt_max : wt, 256, 0, d_tail, ntl});
+    if (wt > 0 || use_graph) L.push_back({batch_tail_fn(), use_graph ? wt_max : wt, 256, 0, d_tail, ntl});
 
     hipStream_t cs = (hipStream_t)stream;
-    hipStream_t s = use_graph ? b->gstream : cs;
     PFBS_HIP(p0, hipSetDevice(p0->device));
-    if (use_graph) {
-        PFBS_HIP(p0, hipEventRecord(b->ev_in, cs));
-        PFBS_HIP(p0, hipStreamWaitEvent(s, b->ev_in, 0));
-    }
-    PFBS_HIP(p0, hipMemcpyAsync(b->d_tab, &T, sizeof T, hipMemcpyHostToDevice, s));
-    PFBS_HIP(p0, hipEventRecord(b->staged[k], s));
-    b->stage ^= 1;
+    // upload on the copy stream once the kernels that last read this device
+    // buffer are done; the caller's stream waits only for the upload (done
+    // long before, while it ran the blocks in between)
+    PFBS_HIP(p0, hipStreamWaitEvent(b->cstream, b->done[k], 0));
+    PFBS_HIP(p0, hipMemcpyAsync(b->d_tab[k], &T, sizeof T, hipMemcpyHostToDevice, b->cstream));
+    PFBS_HIP(p0, hipEventRecord(b->copied[k], b->cstream));
+    PFBS_HIP(p0, hipStreamWaitEvent(cs, b->copied[k], 0));
+    b->launches = 0;
     if (!use_graph) {
         for (const BLaunch &x : L) {
-            if (x.n == 0) continue;
+            if (x.grid <= 0) continue;
             void *args[] = {(void *)&x.table, (void *)&x.n};
-            PFBS_HIP(p0, hipLaunchKernel(x.fn, dim3(x.grid > 0 ? x.grid : 1), dim3(x.threads), args, x.lds, s));
+            PFBS_HIP(p0, hipLaunchKernel(x.fn, dim3(x.grid), dim3(x.threads), args, x.lds, cs));
+            ++b->launches;
         }
     } else {
-        if (!b->gexec) {
+        if (!b->gexec[k]) {
+            hipStream_t s = b->gstream;
             PFBS_HIP(p0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             hipError_t le = hipSuccess;
             for (const BLaunch &x : L) {
@@ -1246,21 +1272,31 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             }
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(s, &g);
-            if (le != hipSuccess) return hip_fail(p0, le, "batch capture launch");
+            if (le != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(p0, le, "batch capture launch");
+            }
             if (ce != hipSuccess) return hip_fail(p0, ce, "batch capture");
-            b->graph = g;
-            PFBS_HIP(p0, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
-            b->gsizes = sizes;
+            b->graph[k] = g;
+            PFBS_HIP(p0, hipGraphInstantiate(&b->gexec[k], b->graph[k], nullptr, nullptr, 0));
+            b->gsizes[k] = sizes;
         }
-        PFBS_HIP(p0, hipGraphLaunch(b->gexec, s));
-        PFBS_HIP(p0, hipEventRecord(b->ev_out, s));
-        PFBS_HIP(p0, hipStreamWaitEvent(cs, b->ev_out, 0));
+        // captured on the batch's own stream, replayed on the caller's
+        PFBS_HIP(p0, hipGraphLaunch(b->gexec[k], cs));
+        b->launches = (int)L.size();
     }
+    PFBS_HIP(p0, hipEventRecord(b->done[k], cs));
+    b->stage = (b->stage + 1) % pfbs_batch::kTabRing;
     for (int i = 0; i < n; ++i) {
         commit(b->plans[i], w[i]);
         n_dumps[i] = w[i].nd_out;
     }
     return PFBS_OK;
+}
+
+int32_t pfbs_batch_launches(const pfbs_batch *b) {
+    if (!b || b->magic != kMagic) return -1;
+    return b->launches;
 }
 
 pfbs_status pfbs_batch_destroy(pfbs_batch *b) {

@@ -29,7 +29,7 @@ EXPORTS = (
     "pfbs_batch_destroy", "pfbs_batch_plan", "pfbs_plan_timing", "pfbs_plan_timing_read",
     "pfbs_autotune", "pfbs_host_alloc", "pfbs_host_free", "pfbs_hstream_create", "pfbs_hstream_push",
     "pfbs_hstream_sync", "pfbs_hstream_destroy", "pfbs_hstream_plan", "pfbs_version", "pfbs_plan_timing_kinds",
-    "pfbs_execute_noalloc", "pfbs_debug_table",
+    "pfbs_execute_noalloc", "pfbs_debug_table", "pfbs_batch_launches",
 )
 
 KERNEL_KINDS = ("single_pass", "column_pass", "row_pass", "dump_reduce", "tap_history")
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
     L.pfbs_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), i32]
     L.pfbs_batch_execute.argtypes = [vp, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64, pi64, i32, vp]
     L.pfbs_batch_destroy.argtypes = [vp]
+    L.pfbs_batch_launches.argtypes = [vp]
+    L.pfbs_batch_launches.restype = i32
     L.pfbs_plan_timing.argtypes = [vp, i32]
     L.pfbs_plan_timing_kinds.argtypes = [vp, ctypes.c_uint32]
     L.pfbs_plan_timing_kinds.restype = ctypes.c_int
@@ -302,7 +304,7 @@ class Plan:
 
 
 class Batch:
-    """Several sub-band streams run by one launch sequence (pfbs_batch)."""
+    """Several sub-band streams run by three launches per block (pfbs_batch)."""
 
     def __init__(self, descs: Sequence[PlanDesc]):
         self._lib = load()
@@ -324,6 +326,11 @@ class Batch:
         _check(self._lib.pfbs_batch_execute(self._h, blk, ns, dp, caps, nd, int(use_graph),
                                             _stream_ptr(stream)))
         return list(nd)
+
+    @property
+    def launches(self) -> int:
+        """Kernel launches (or graph kernel nodes) of the last execute."""
+        return int(self._lib.pfbs_batch_launches(self._h))
 
     def close(self):
         if self._h:

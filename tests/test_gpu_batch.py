@@ -1,6 +1,7 @@
-"""Batched multi-sub-band launches: one dispatcher launch per phase for all
-sub-bands (optionally replayed from a HIP graph) must give bit-identical dumps
-to each sub-band's own plan, and match the oracle."""
+"""Batched multi-sub-band launches: three launches per block for all
+sub-bands (front phase, row phase, tail; optionally replayed from a HIP
+graph) must give bit-identical dumps to each sub-band's own plan, in FP32 and
+MIXED, and match the oracle."""
 import numpy as np
 import pytest
 
@@ -31,17 +32,19 @@ def _descs():
     return [pf.make_desc(N=N, P=P, mode=m, n_pol=2, n_int=ni) for (N, P, m, ni) in SUBBANDS]
 
 
-def _run_batch(xs, use_graph):
+def _run_batch(xs, use_graph, descs=None, subs=SUBBANDS, launches=None):
     torch = require_gpu()
-    b = pf.Batch(_descs())
+    b = pf.Batch(descs or _descs())
     outs = [[] for _ in SUBBANDS]
     for k in range(BLOCKS):
         blocks = [torch.from_numpy(np.ascontiguousarray(x[k * BLOCK:(k + 1) * BLOCK])).cuda() for x in xs]
         dumps = [torch.empty((max(p.dumps_in(BLOCK), 1), 4, p.N), dtype=torch.float32, device="cuda")
                  for p in b.plans]
         nd = b.execute(blocks, dumps, use_graph=use_graph)
+        if launches is not None:
+            launches.append(b.launches)
         torch.cuda.synchronize()
-        for i in range(len(SUBBANDS)):
+        for i in range(len(subs)):
             if nd[i]:
                 outs[i].append(dumps[i][:nd[i]].cpu().numpy())
     parts = []
@@ -49,7 +52,7 @@ def _run_batch(xs, use_graph):
         part = torch.empty((4, p.N), dtype=torch.float32, device="cuda")
         parts.append((p.flush(part), part))
     torch.cuda.synchronize()
-    res = [np.concatenate(o) if o else np.zeros((0, 4, SUBBANDS[i][0]), np.float32) for i, o in enumerate(outs)]
+    res = [np.concatenate(o) if o else np.zeros((0, 4, subs[i][0]), np.float32) for i, o in enumerate(outs)]
     flushed = [(c, t.cpu().numpy()) for c, t in parts]
     b.close()
     return res, flushed
@@ -59,7 +62,9 @@ def _run_batch(xs, use_graph):
 def test_batched_equals_individual_plans_bitwise(use_graph):
     require_gpu()
     xs = _streams()
-    got, flushed = _run_batch(xs, use_graph)
+    launches = []
+    got, flushed = _run_batch(xs, use_graph, launches=launches)
+    assert launches == [3] * BLOCKS
     for i, ((N, P, m, ni), x) in enumerate(zip(SUBBANDS, xs)):
         plan = pf.Plan(N, P, mode=m, n_pol=2, n_int=ni)
         want, part, cnt = run_stream(plan, x, [BLOCK // N])
@@ -83,11 +88,10 @@ def test_batched_graph_replays_match_oracle():
 
 @pytest.mark.parametrize("n_pol", [2, 1])
 def test_two_spectra_column_kernel_bitwise(n_pol):
-    """Where the tap table is large (P*N >= 2^21 floats) a plan's FP32 column
-    pass filters two spectra per workgroup step; batches run the one-spectrum
-    kernel.  Both do the same arithmetic in the same order, so one sub-band
-    batched and alone agree bit for bit, with odd and even spectrum counts
-    per block (5, 11 and 10 here)."""
+    """Where the tap table is large (P*N >= 2^21 floats) an FP32 column pass
+    filters two spectra per workgroup step, in a plan's own launch and in the
+    batched front phase alike: one sub-band batched and alone agree bit for
+    bit, with odd and even spectrum counts per block (5, 11 and 10 here)."""
     torch = require_gpu()
     N, P, ni = 262144, 8, 3
     frames = [12, 11, 10]
@@ -144,3 +148,61 @@ def test_graph_grid_covers_padded_column_items():
         want, _part, _cnt = run_stream(pf.Plan(N, P, mode=m, n_pol=2, n_int=ni), xs[i], frames)
         g = np.concatenate(got[i])
         assert g.shape == want.shape and np.array_equal(g, want), i
+
+
+# FP32 and MIXED sub-bands in one batch: single pass, one-spectrum and
+# two-spectra column passes, FP32, FP64 and split-FP16 row passes
+MIXED_SUBBANDS = [
+    (1024, 8, pf.MODE_PFB, 40, pf.PREC_MIXED),
+    (16384, 4, pf.MODE_PFB, 6, pf.PREC_MIXED),
+    (65536, 1, pf.MODE_DIRECT, 3, pf.PREC_FP32),
+    (131072, 8, pf.MODE_PFB, 2, pf.PREC_MIXED),
+    (262144, 8, pf.MODE_PFB, 2, pf.PREC_FP32),
+    (524288, 4, pf.MODE_PFB, 2, pf.PREC_MIXED),
+]
+MIXED_BLOCK = 1 << 21
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_mixed_precision_batch_bitwise(use_graph):
+    require_gpu()
+    subs = [s[:4] for s in MIXED_SUBBANDS]
+    descs = [pf.make_desc(N=N, P=P, mode=m, n_pol=2, n_int=ni, precision=pr) for (N, P, m, ni, pr) in MIXED_SUBBANDS]
+    xs = [synth.generate(synth.spec_subband(s, N), 11, MIXED_BLOCK * 3) for s, (N, *_r) in enumerate(subs)]
+    torch = require_gpu()
+    b = pf.Batch(descs)
+    assert [p.info()["row_arith"] for p in b.plans[1:]] == [2, 0, 2, 3, 2]
+    outs = [[] for _ in subs]
+    for k in range(3):
+        blocks = [torch.from_numpy(np.ascontiguousarray(x[k * MIXED_BLOCK:(k + 1) * MIXED_BLOCK])).cuda() for x in xs]
+        dumps = [torch.empty((max(p.dumps_in(MIXED_BLOCK), 1), 4, p.N), dtype=torch.float32, device="cuda")
+                 for p in b.plans]
+        nd = b.execute(blocks, dumps, use_graph=use_graph)
+        assert b.launches == 3
+        torch.cuda.synchronize()
+        for i in range(len(subs)):
+            if nd[i]:
+                outs[i].append(dumps[i][:nd[i]].cpu().numpy())
+    b.close()
+    for i, (N, P, m, ni, pr) in enumerate(MIXED_SUBBANDS):
+        want, _part, _cnt = run_stream(pf.Plan(N, P, mode=m, n_pol=2, n_int=ni, precision=pr), xs[i],
+                                       [MIXED_BLOCK // N] * 3)
+        g = np.concatenate(outs[i])
+        assert g.shape == want.shape and np.array_equal(g, want), i
+
+
+def test_batch_of_single_pass_sub_bands_only_has_no_row_phase():
+    """Only single-pass sub-bands: the front phase and the tail, two launches."""
+    torch = require_gpu()
+    subs = [(256, 4, pf.MODE_PFB, 16), (4096, 1, pf.MODE_DIRECT, 8)]
+    xs = [synth.generate(synth.spec_subband(s, N), 2, 1 << 17) for s, (N, *_r) in enumerate(subs)]
+    b = pf.Batch([pf.make_desc(N=N, P=P, mode=m, n_pol=2, n_int=ni) for (N, P, m, ni) in subs])
+    dumps = [torch.empty((max(p.dumps_in(1 << 17), 1), 4, p.N), dtype=torch.float32, device="cuda") for p in b.plans]
+    nd = b.execute([torch.from_numpy(x).cuda() for x in xs], dumps)
+    assert b.launches == 2
+    torch.cuda.synchronize()
+    got = [dumps[i][:nd[i]].cpu().numpy() for i in range(2)]
+    b.close()
+    for i, (N, P, m, ni) in enumerate(subs):
+        want, _p, _c = run_stream(pf.Plan(N, P, mode=m, n_pol=2, n_int=ni), xs[i], [(1 << 17) // N])
+        assert np.array_equal(got[i], want), i

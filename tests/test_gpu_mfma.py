@@ -140,8 +140,8 @@ def test_fp16x2_silence_and_tiny_signal():
     assert within_fp32_bound(d[0], ref, N) <= 1.0
 
 
-def test_batch_rejects_matrix_core_precisions_and_output_forms():
-    for kw in (dict(precision=X2), dict(precision=MIX), dict(output=pf.OUT_STOKES), dict(fftshift=1)):
+def test_batch_rejects_matrix_core_front_precisions_and_output_forms():
+    for kw in (dict(precision=X2), dict(precision=F16), dict(output=pf.OUT_STOKES), dict(fftshift=1)):
         desc = pf.make_desc(N=4096, P=8, n_pol=2, n_int=4, **kw)
         with pytest.raises(pf.PfbsError):
             pf.Batch([desc])
