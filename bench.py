@@ -169,9 +169,21 @@ def bench_subbands(args):
     t_gen = time.perf_counter() - t_gen
     blocks = [[torch.from_numpy(parts[b * len(SUBBANDS) + s]).cuda() for s in range(len(SUBBANDS))]
               for b in range(nblk)]
+    # every sub-band's speed-only fields from the autotuner at the sub-block
+    # size (or the chunk given on the command line)
+    t_tune = time.perf_counter()
+    knobs = []
+    for (N, P, d, ni) in SUBBANDS:
+        if args.no_tune or args.chunk:
+            knobs.append({"chunk": args.chunk})
+        else:
+            f, _ = pf.autotune(block_samples=sub, N=N, P=P, mode=pf.MODE_DIRECT if d else pf.MODE_PFB, n_pol=2,
+                               n_int=ni, precision=prec)
+            knobs.append({k: f[k] for k in KNOBS})
+    t_tune = time.perf_counter() - t_tune
     descs = [pf.make_desc(N=N, P=P, mode=pf.MODE_DIRECT if d else pf.MODE_PFB, n_pol=2, n_int=ni,
-                          precision=prec, chunk=args.chunk)
-             for (N, P, d, ni) in SUBBANDS]
+                          precision=prec, **kn)
+             for (N, P, d, ni), kn in zip(SUBBANDS, knobs)]
     samples_per_block = len(SUBBANDS) * sub * 2
     # the first few dozen executes of a process stall now and then (runtime
     # start-up); run them before any timed mode
@@ -185,8 +197,8 @@ def bench_subbands(args):
     for mode in ("batched", "graph", "individual"):
         if mode == "individual":
             plans = [pf.Plan(N, P, mode=pf.MODE_DIRECT if d else pf.MODE_PFB, n_pol=2, n_int=ni, precision=prec,
-                             chunk=args.chunk)
-                     for (N, P, d, ni) in SUBBANDS]
+                             **kn)
+                     for (N, P, d, ni), kn in zip(SUBBANDS, knobs)]
         else:
             batch = pf.Batch(descs)
             plans = batch.plans
@@ -217,6 +229,8 @@ def bench_subbands(args):
         else:
             for p in plans:
                 p.close()
+    results["knobs"] = knobs
+    results["tune_s"] = round(t_tune, 1)
     return results, t_gen
 
 
@@ -388,7 +402,25 @@ def first_dump_error(w, prec, dev_blocks, ref, **plan_kw):
                      np.max(np.abs(got[2] - ref[2]) / sc), np.max(np.abs(got[3] - ref[3]) / sc)))
 
 
-def time_path(w, prec_name, dev_blocks, args):
+KNOBS = ("split_n2", "chunk", "col_run", "stream_z", "tap_unroll", "col_pair", "row_tile")
+
+
+def plan_knobs(w, prec_name, args):
+    """The speed-only plan fields of one path: the autotuner's choice for this
+    shape and block size (pfbs_autotune's coordinate search), or the ones given
+    on the command line (then nothing is tuned)."""
+    from paper_1411_0436_amd import pfbspec as pf
+    given = {"split_n2": args.split_n2, "chunk": args.chunk, "tap_unroll": args.tap_unroll,
+             "col_pair": args.col_pair, "row_tile": args.row_tile}
+    if args.no_tune or any(given.values()):
+        return dict(given), False
+    fields, _ = pf.autotune(block_samples=w["block"], N=w["N"], P=w["P"],
+                            mode=pf.MODE_DIRECT if w["direct"] else pf.MODE_PFB, n_pol=w["n_pol"],
+                            n_int=w["n_int"], precision=PRECISIONS[prec_name])
+    return {k: fields[k] for k in KNOBS}, True
+
+
+def time_path(w, prec_name, dev_blocks, args, knobs):
     """Time `steps` passes of the whole stream through one plan of the given
     precision (after `warmup` untimed ones).  Kernel times come from the
     library's dispatch timestamps: every kind during the warm-up, only the
@@ -397,9 +429,7 @@ def time_path(w, prec_name, dev_blocks, args):
     from paper_1411_0436_amd import pfbspec as pf
     N = w["N"]
     plan = pf.Plan(N, w["P"], mode=pf.MODE_DIRECT if w["direct"] else pf.MODE_PFB, n_pol=w["n_pol"],
-                   n_int=w["n_int"], split_n2=args.split_n2, chunk=args.chunk,
-                   group_bytes=args.group_mb << 20, precision=PRECISIONS[prec_name],
-                   tap_unroll=args.tap_unroll, col_pair=args.col_pair)
+                   n_int=w["n_int"], group_bytes=args.group_mb << 20, precision=PRECISIONS[prec_name], **knobs)
     info = plan.info()
     cap = max(plan.dumps_in(w["block"]) + 1, 2)
     dumps = torch.empty((cap, plan.n_prod, N), dtype=torch.float32, device="cuda")
@@ -473,15 +503,20 @@ def bench_stream(args):
         del x
 
     paths = {}
+    t_tune = 0.0
     for p in precs:
-        r = time_path(w, p, dev_blocks, args)
+        t0 = time.perf_counter()
+        knobs, tuned = plan_knobs(w, p, args)
+        t_tune += time.perf_counter() - t0
+        r = time_path(w, p, dev_blocks, args, knobs)
+        r["knobs"], r["tuned"] = knobs, tuned
         if ref is not None:
-            r["max_rel_err"] = first_dump_error(w, PRECISIONS[p], dev_blocks, ref, split_n2=args.split_n2,
-                                                chunk=args.chunk, group_bytes=args.group_mb << 20,
-                                                tap_unroll=args.tap_unroll, col_pair=args.col_pair)
+            r["max_rel_err"] = first_dump_error(w, PRECISIONS[p], dev_blocks, ref,
+                                                group_bytes=args.group_mb << 20, **knobs)
         paths[p] = r
-        print("bench: %s %.2f Gsamples/s%s" % (p, r["value"], "" if ref is None else
-                                                ", first-dump error %.3g" % r["max_rel_err"]),
+        print("bench: %s %.2f Gsamples/s%s, %s %s" % (p, r["value"], "" if ref is None else
+                                                      ", first-dump error %.3g" % r["max_rel_err"],
+                                                      "tuned" if tuned else "given", knobs),
               file=sys.stderr, flush=True)
     ok = [p for p in precs if ref is None or paths[p]["max_rel_err"] <= 1e-5]
     best = max(ok or precs, key=lambda p: paths[p]["value"])
@@ -518,7 +553,9 @@ def bench_stream(args):
         "config": {"workload": args.workload, "N": N, "P": w["P"], "mode": "direct" if w["direct"] else "pfb",
                    "n_pol": n_pol, "n_int": w["n_int"], "block_samples": w["block"],
                    "block_MB": w["block"] * 2 * n_pol >> 20, "blocks": w["blocks"], "precision": best,
-                   "split_n1": info["split_n1"], "split_n2": info["split_n2"], "chunk": info["chunk"]},
+                   "split_n1": info["split_n1"], "split_n2": info["split_n2"], "chunk": info["chunk"],
+                   "row_tile": info["row_tile"], "knobs": r["knobs"], "tuned": r["tuned"],
+                   "tune_s": round(t_tune, 1)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(tflops, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
@@ -545,6 +582,7 @@ def bench_stream(args):
                       "max_rel_err_first_dump": None if "max_rel_err" not in q else float("%.3g" % q["max_rel_err"]),
                       "within_1e-5": None if "max_rel_err" not in q else bool(q["max_rel_err"] <= 1e-5),
                       "split_n2": q["info"]["split_n2"], "row_arith": q["info"]["row_arith"],
+                      "knobs": q["knobs"], "tuned": q["tuned"],
                       "dominant": q["dominant"], "kernel_ms": q["kernel_ms"],
                       "launches_per_step": q["kernel_launches_per_step"]}
                   for p, q in paths.items()},
@@ -578,6 +616,9 @@ def main():
     ap.add_argument("--tap-unroll", type=int, default=0, help="pre-filter tap loop (0 auto, 1 unrolled, 2 loop)")
     ap.add_argument("--col-pair", type=int, default=0, help="two-spectra column kernel (0 auto, 1 on, 2 off)")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--row-tile", type=int, default=0, help="row-pass tile points (0 auto)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="plans with their built-in choices instead of the autotuner's")
     ap.add_argument("--c5-precision", default="fp32", choices=["fp32", "mixed"],
                     help="c5: precision of every sub-band")
     ap.add_argument("--blocks", type=int, default=0, help="override the workload's block count")

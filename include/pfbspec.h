@@ -127,8 +127,9 @@ typedef enum { PFBS_OUT_PRODUCTS = 0, PFBS_OUT_STOKES = 1 } pfbs_output;
  *                 two-pass intermediate, 0 = ordinary ones;
  *   tap_unroll, col_pair: see the fields (speed only; the same arithmetic in
  *                 the same order either way, so the same bits).
- * chunk, split_n2, group_bytes, col_run, stream_z, tap_unroll and col_pair
- * only change speed, never results beyond FP32 rounding order.
+ * chunk, split_n2, group_bytes, col_run, stream_z, tap_unroll, col_pair and
+ * row_tile only change speed, never results beyond FP32 rounding order
+ * (tap_unroll, col_pair and row_tile not even that: same bits).
  * With tune = 1 they are taken from the autotune cache when it holds an
  * entry for this device and shape (see pfbs_autotune); with tune = 2 a
  * missing entry is measured first.                                          */
@@ -155,6 +156,11 @@ typedef struct {
     int32_t col_pair;   /* column pass on two spectra per workgroup step (pre-filter
                            with 4-point columns of at most 256, PFB mode): 0
                            automatic, 1 where it applies, 2 never */
+    int32_t row_tile;   /* row pass of the two-pass FFT: points per polarisation per
+                           workgroup step (TP/N1 rows of N1 points, TP/16 threads
+                           per polarisation): 0 = max(1024, N1), else 1024, 2048
+                           or 4096, at least N1 (PFBS_ERR_INVALID otherwise);
+                           ignored for N <= 4096 */
 } pfbs_plan_desc;
 
 /* Create a plan (FP32 arithmetic; Section 4, initialisation: coefficients are
@@ -280,7 +286,8 @@ typedef struct {
                                        FFT: 0 FP32, 1 FP16 matrix cores, 2 split
                                        FP16 matrix cores, 3 FP64 (FP32 plans from
                                        2^18 channels); -1 for a single-pass FFT */
-    int32_t pad_;
+    int32_t row_tile;               /* row-pass tile points per polarisation (0 for
+                                       N <= 4096) */
 } pfbs_plan_info;
 
 pfbs_status pfbs_plan_get_info(const pfbs_plan *plan, pfbs_plan_info *info);
@@ -299,18 +306,24 @@ pfbs_status pfbs_plan_timing(pfbs_plan *plan, int32_t enable);
 pfbs_status pfbs_plan_timing_kinds(pfbs_plan *plan, uint32_t kinds);
 pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches, int32_t n);
 
-/* Autotuner.  Times candidate settings of the speed-only fields (split_n2,
- * chunk, col_run, stream_z, tap_unroll, col_pair) for the plan shape in *desc on its device, each
- * on the same synthetic stream of device blocks of block_samples time samples
- * (a positive multiple of N; 0 = 2^24; as many distinct blocks as make at
- * least 512 MB, at most 16, so the input streams from HBM and not from the
- * caches), with HIP events around two passes over them, and
- * writes the fastest into *best (a copy of *desc with those fields set and
- * tune = 0) and its throughput in complex samples per second into
- * *best_samples_per_s (may be NULL).  At most max_candidates settings are
- * timed (0 = all).  If the environment variable PFBS_TUNE_CACHE names a file,
- * the result is appended to it as one text line
- *   pfbs-tune-v3 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z tap_unroll col_pair samples_per_s
+/* Autotuner.  Times candidate settings of the speed-only fields for the plan
+ * shape in *desc on its device: split_n2 (the radix split of the two-pass
+ * FFT, limited to splits that keep the precision's accuracy: rows no longer
+ * than the default split's, or any split where the rows run in FP64),
+ * col_pair (column-pass workgroups of one or two spectra: 8 or 16 waves),
+ * tap_unroll, row_tile (row-pass tile width, hence waves per workgroup),
+ * chunk, col_run and stream_z.  The search is coordinate-wise: each field in
+ * turn over its values, the others at their best so far, starting from the
+ * plan's automatic choices.  Each candidate runs on the same synthetic stream
+ * of device blocks of block_samples time samples (a positive multiple of N;
+ * 0 = 2^24; as many distinct blocks as make at least 512 MB, at most 16, so
+ * the input streams from HBM and not from the caches), timed with HIP events
+ * around two passes over them.  Writes the fastest into *best (a copy of
+ * *desc with those fields set and tune = 0) and its throughput in complex
+ * samples per second into *best_samples_per_s (may be NULL).  At most
+ * max_candidates settings are timed (0 = all).  If the environment variable
+ * PFBS_TUNE_CACHE names a file, the result is appended to it as one text line
+ *   pfbs-tune-v4 <arch> <version> N P mode n_pol n_int precision block split_n2 chunk col_run stream_z tap_unroll col_pair row_tile samples_per_s
  * (version: the source digest of pfbs_version, so a rebuilt library with
  * changed kernels does not reuse old measurements)
  * and later plans created with tune != 0 reuse the newest matching line.

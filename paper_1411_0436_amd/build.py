@@ -16,8 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfbspec.so")
 RUNNER = os.path.join(HERE, "pfbs_run")
-SOURCES = ["k_single.hip", "k_fourstep.hip", "k_batch.hip", "k_aux.hip", "plan.cpp", "autotune.cpp", "host_stream.cpp"]
-HEADERS = ["pfbs_internal.h", "fft_common.h", os.path.join("..", "..", "include", "pfbspec.h")]
+SOURCES = ["k_single.hip", "k_fourstep.hip", "k_rows_f32.hip", "k_rows_mfma.hip", "k_batch.hip", "k_aux.hip", "plan.cpp", "autotune.cpp", "host_stream.cpp"]
+HEADERS = ["pfbs_internal.h", "fft_common.h", "fft_bodies.h", "k_rows.h", os.path.join("..", "..", "include", "pfbspec.h")]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

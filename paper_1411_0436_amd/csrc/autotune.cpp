@@ -1,8 +1,13 @@
-// Autotuner for the speed-only plan fields (split of the two-pass FFT, chunk
-// length of the partial integrations, spectra per column-pass workgroup,
-// streaming intermediate).  Every candidate computes the same spectra; they
-// differ only in how the work is cut and scheduled on the device.  Candidates
-// are timed with HIP events on one synthetic device block and the fastest is
+// Autotuner for the speed-only plan fields: the radix split of the two-pass
+// FFT (column length), the column pass's workgroup form (one or two spectra
+// per step: 8 or 16 waves), the pre-filter's tap loop, the row pass's tile
+// width (rows per workgroup step, hence its waves per workgroup), the chunk
+// length of the partial integrations, spectra per column-pass workgroup and
+// the streaming intermediate.  Every candidate computes the same spectra to
+// the precision's accuracy (splits are limited by split_keeps_accuracy); they
+// differ in how the work is cut and scheduled on the device.  Candidates are
+// timed with HIP events on synthetic device blocks in a coordinate search
+// (each field in turn, the others at their best so far) and the fastest is
 // kept, optionally in a plain-text cache file (PFBS_TUNE_CACHE).
 #include <hip/hip_runtime.h>
 
@@ -40,16 +45,16 @@ std::string device_arch() {
 struct Line {
     std::string arch, version;
     long long N, n_int, block, split;
-    int P, mode, npol, prec, chunk, col_run, stream_z, tap_unroll, col_pair;
+    int P, mode, npol, prec, chunk, col_run, stream_z, tap_unroll, col_pair, row_tile;
     double sps;
 };
 
 bool parse(const char *s, Line &l) {
     char tag[32], arch[64], ver[64];
-    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %d %lf", tag, arch, ver, &l.N,
+    int n = sscanf(s, "%31s %63s %63s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %d %d %lf", tag, arch, ver, &l.N,
                    &l.P, &l.mode, &l.npol, &l.n_int, &l.prec, &l.block, &l.split, &l.chunk, &l.col_run,
-                   &l.stream_z, &l.tap_unroll, &l.col_pair, &l.sps);
-    if (n != 17 || strcmp(tag, "pfbs-tune-v3") != 0) return false;
+                   &l.stream_z, &l.tap_unroll, &l.col_pair, &l.row_tile, &l.sps);
+    if (n != 18 || strcmp(tag, "pfbs-tune-v4") != 0) return false;
     l.arch = arch;
     l.version = ver;
     return true;
@@ -87,15 +92,16 @@ void cache_append(const pfbs_plan_desc *d, int64_t block, const pfbs_plan_desc *
     std::lock_guard<std::mutex> lk(g_cache_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "pfbs-tune-v3 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %d %.6e\n", device_arch().c_str(),
+    fprintf(f, "pfbs-tune-v4 %s %s %lld %d %d %d %lld %d %lld %lld %d %d %d %d %d %d %.6e\n", device_arch().c_str(),
             PFBS_SOURCE_DIGEST, (long long)d->N, d->P, d->mode, d->n_pol, (long long)d->n_int, d->precision,
-            (long long)block, (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, b->tap_unroll, b->col_pair, sps);
+            (long long)block, (long long)b->split_n2, b->chunk, b->col_run, b->stream_z, b->tap_unroll, b->col_pair,
+            b->row_tile, sps);
     fclose(f);
 }
 
-// Valid column lengths of the two-pass FFT for N (mirrors the plan's checks).
-// Column lengths worth timing: every one the kernels support.
-std::vector<int64_t> splits_for(int64_t N) {
+// Column lengths worth timing: every one the kernels support for N that
+// keeps the precision's accuracy (0 = one pass).
+std::vector<int64_t> splits_for(int64_t N, int precision) {
     std::vector<int64_t> v;
     if (N <= pfbs::kMaxSinglePass) {
         v.push_back(0);
@@ -105,7 +111,9 @@ std::vector<int64_t> splits_for(int64_t N) {
         const int64_t n1 = N / n2;
         if (n1 < 32 || n1 > pfbs::kMaxSinglePass) continue;
         const int tb = pfbs::back_tile_points(n1);
-        if (n1 % (pfbs::kTilePoints / n2) == 0 && n2 % (tb / n1) == 0) v.push_back(n2);
+        if (n1 % (pfbs::kTilePoints / n2) == 0 && n2 % (tb / n1) == 0 &&
+            pfbs::split_keeps_accuracy(N, precision, n2))
+            v.push_back(n2);
     }
     return v;
 }
@@ -153,6 +161,7 @@ pfbs_status tune_lookup(const pfbs_plan_desc *desc, bool measure_if_missing, pfb
         out->stream_z = l.stream_z;
         out->tap_unroll = l.tap_unroll;
         out->col_pair = l.col_pair;
+        out->row_tile = l.row_tile;
         return PFBS_OK;
     }
     if (!measure_if_missing) return PFBS_OK;
@@ -176,35 +185,33 @@ extern "C" pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_s
     if (n / base.N < need) n = need * base.N;
     if (base.device >= 0 && hipSetDevice(base.device) != hipSuccess) return PFBS_ERR_DEVICE;
 
-    // candidate list: every valid split x chunk x run length; streaming off
-    std::vector<pfbs_plan_desc> cands;
-    const std::vector<int64_t> splits = splits_for(base.N);
+    // the fields searched, each with its values (0: the plan's automatic choice)
     const bool four = base.N > pfbs::kMaxSinglePass;
-    const int chunks[] = {8, 16, 32, 64};
-    const int runs[] = {1, 2, 4};
-    // the tap loop's form matters only with the filter at 4 or 8 taps
     const bool unrollable = base.mode == PFBS_MODE_PFB && (base.P == 4 || base.P == 8);
-    for (int64_t sp : splits)
-        for (int ch : chunks)
-            for (int r = 0; r < (four ? 3 : 1); ++r)
-                for (int u = unrollable ? 1 : 0; u <= (unrollable ? 2 : 0); ++u) {
-                    pfbs_plan_desc c = base;
-                    c.split_n2 = sp;
-                    c.chunk = ch;
-                    c.col_run = four ? runs[r] : 0;
-                    c.stream_z = 0;
-                    c.group_bytes = 0;
-                    c.tap_unroll = u;
-                    cands.push_back(c);
-                }
-    if (four) {  // streaming intermediate, at the default split
-        pfbs_plan_desc c = base;
-        c.stream_z = 1;
-        c.col_run = 1;
-        cands.push_back(c);
+    struct Field {
+        int64_t pfbs_plan_desc::*wide;
+        int32_t pfbs_plan_desc::*narrow;
+        std::vector<int64_t> values;
+    };
+    std::vector<Field> fields;
+    if (four) {
+        fields.push_back({&pfbs_plan_desc::split_n2, nullptr, splits_for(base.N, base.precision)});
+        if (base.mode == PFBS_MODE_PFB) fields.push_back({nullptr, &pfbs_plan_desc::col_pair, {2, 1}});
     }
-    if (max_candidates > 0 && (int)cands.size() > max_candidates) cands.resize(max_candidates);
-
+    if (unrollable) fields.push_back({nullptr, &pfbs_plan_desc::tap_unroll, {2, 1}});
+    if (four) fields.push_back({nullptr, &pfbs_plan_desc::row_tile, {0, 2048, 4096}});
+    fields.push_back({nullptr, &pfbs_plan_desc::chunk, {4, 8, 16, 32, 64}});
+    if (four) {
+        fields.push_back({nullptr, &pfbs_plan_desc::col_run, {1, 2, 4}});
+        fields.push_back({nullptr, &pfbs_plan_desc::stream_z, {0, 1}});
+    }
+    auto get = [](const pfbs_plan_desc &d, const Field &f) -> int64_t { return f.wide ? d.*f.wide : d.*f.narrow; };
+    auto set = [](pfbs_plan_desc &d, const Field &f, int64_t v) {
+        if (f.wide) d.*f.wide = v;
+        else d.*f.narrow = (int32_t)v;
+    };
+    base.group_bytes = 0;
+    if (four && base.split_n2 == 0) base.split_n2 = pfbs::default_split(base.N);
     const size_t bytes = (size_t)n * 2 * base.n_pol;
     // enough distinct blocks (at least 512 MB, at most 16) that the input
     // streams from HBM as in a real run instead of staying in the caches
@@ -222,14 +229,29 @@ extern "C" pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_s
     }
     double best_t = -1.0;
     pfbs_plan_desc winner = base;
+    int timed_n = 0;
     if (rs == PFBS_OK && pfbs::launch_synth((uint32_t *)d_block, (long long)(bytes * nb / 4), 0x5eedu, s) != hipSuccess)
         rs = PFBS_ERR_DEVICE;
+    auto try_cand = [&](const pfbs_plan_desc &c) {
+        if (max_candidates > 0 && timed_n >= max_candidates) return;
+        pfbs_plan_desc v = c;
+        if (pfbs::validate_desc_quiet(&v) != PFBS_OK) return;  // e.g. a row tile shorter than the rows
+        ++timed_n;
+        const double t = time_candidate(&v, (const uint8_t *)d_block, nb, n, d_dumps, cap, s, 1, 2);
+        if (t > 0 && (best_t < 0 || t < best_t)) {
+            best_t = t;
+            winner = v;
+        }
+    };
     if (rs == PFBS_OK) {
-        for (const pfbs_plan_desc &c : cands) {
-            const double t = time_candidate(&c, (const uint8_t *)d_block, nb, n, d_dumps, cap, s, 1, 2);
-            if (t > 0 && (best_t < 0 || t < best_t)) {
-                best_t = t;
-                winner = c;
+        try_cand(base);
+        for (const Field &f : fields) {
+            const pfbs_plan_desc cur = winner;
+            for (int64_t v : f.values) {
+                if (v == get(cur, f)) continue;
+                pfbs_plan_desc c = cur;
+                set(c, f, v);
+                try_cand(c);
             }
         }
         if (best_t < 0) rs = PFBS_ERR_DEVICE;

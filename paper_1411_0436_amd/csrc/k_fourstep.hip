@@ -29,14 +29,8 @@ __global__ __launch_bounds__(kTilePoints / 16 * NPOL * 2) void k_front_cols_pair
     front_cols_pair_body<NPOL, L, PT, PREC>(a, blockIdx.x, gridDim.x, threadIdx.x, smem);
 }
 
-template <int NPOL, int L, int PREC>
-__global__ __launch_bounds__(BackTile<L>::TP / 16 * NPOL) void k_back(BackArgs a) {
-    extern __shared__ float smem[];
-    back_body<NPOL, L, PREC>(a, blockIdx.x, threadIdx.x, smem);
-}
 
 #define PFBS_COLS_CASES(X) X(64) X(128) X(256) X(512)
-#define PFBS_BACK_CASES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 namespace {
 template <int PREC>
@@ -68,22 +62,6 @@ hipError_t launch_cols_p(const FrontArgs &a, int npol, bool pfb, dim3 grid, dim3
 }
 
 template <int PREC>
-hipError_t launch_back_p(const BackArgs &a, int npol, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    switch (a.g.L) {
-#define PFBS_CASE(LL)                                                                     \
-    case LL:                                                                              \
-        if (npol == 2) PFBS_LAUNCH((k_back<2, LL, PREC>), grid, block, lds, s, a); \
-        else PFBS_LAUNCH((k_back<1, LL, PREC>), grid, block, lds, s, a);           \
-        break;
-        PFBS_BACK_CASES(PFBS_CASE)
-#undef PFBS_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int PREC>
 hipError_t init_fourstep_p(int lds_limit) {
     hipError_t e = hipSuccess;
 #define PFBS_ATTR(fn)                                                                            \
@@ -103,24 +81,7 @@ hipError_t init_fourstep_p(int lds_limit) {
     PFBS_ATTR((k_front_cols<1, false, LL, PREC>))
     PFBS_COLS_CASES(PFBS_CASE)
 #undef PFBS_CASE
-#define PFBS_CASE(LL) PFBS_ATTR((k_back<2, LL, PREC>)) PFBS_ATTR((k_back<1, LL, PREC>))
-    PFBS_BACK_CASES(PFBS_CASE)
-#undef PFBS_CASE
 #undef PFBS_ATTR
-    return e;
-}
-// Row kernels only (the FP64 row pass has no column kernels of its own).
-template <int PREC>
-hipError_t init_back_p(int lds_limit) {
-    hipError_t e = hipSuccess;
-#define PFBS_CASE(LL)                                                                                       \
-    for (const void *fn : {reinterpret_cast<const void *>(k_back<2, LL, PREC>),                                \
-                           reinterpret_cast<const void *>(k_back<1, LL, PREC>)}) {                             \
-        hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);       \
-        if (r != hipSuccess) e = r;                                                                         \
-    }
-    PFBS_BACK_CASES(PFBS_CASE)
-#undef PFBS_CASE
     return e;
 }
 }  // namespace
@@ -168,21 +129,18 @@ hipError_t launch_front_cols(const FrontArgs &a, int npol, bool pfb, int prec, i
 }
 
 hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s) {
-    const size_t lds = back_lds_bytes(a.g, npol, prec);
-    const dim3 grid(n_chunks * a.ntiles), block(a.g.T * a.g.L / 16 * npol);
-    switch (prec) {
-    case 0: return launch_back_p<0>(a, npol, grid, block, lds, s);
-    case 1: return launch_back_p<1>(a, npol, grid, block, lds, s);
-    case 2: return launch_back_p<2>(a, npol, grid, block, lds, s);
-    case 3: return a.g.tw64 ? launch_back_p<3>(a, npol, grid, block, lds, s) : hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-    }
+    return prec == 1 || prec == 2 ? launch_back_mfma(a, npol, prec, n_chunks, s)
+                                  : launch_back_vector(a, npol, prec, n_chunks, s);
 }
 
 hipError_t init_fourstep(int lds_limit) {
+    // the row pass: up to 4096-point tiles, FP64 planes (up to 143 KB)
     hipError_t e0 = init_fourstep_p<0>(lds_limit), e1 = init_fourstep_p<1>(lds_limit),
-               e2 = init_fourstep_p<2>(lds_limit), e3 = init_back_p<3>(160 * 1024);
-    return e0 != hipSuccess ? e0 : (e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3));
+               e2 = init_fourstep_p<2>(lds_limit), e3 = init_back_vector(160 * 1024),
+               e4 = init_back_mfma(160 * 1024);
+    for (hipError_t e : {e0, e1, e2, e3, e4})
+        if (e != hipSuccess) return e;
+    return hipSuccess;
 }
 
 bool init_fourstep_pair(int lds_limit) {

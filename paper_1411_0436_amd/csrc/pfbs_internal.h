@@ -25,6 +25,19 @@ constexpr int back_tile_points(long long n1) { return n1 < 1024 ? 1024 : (int)n1
 constexpr int kRowF64 = 3;
 constexpr int fp32_row_precision(long long N) { return N >= (1LL << 18) ? kRowF64 : 0; }
 
+// Column length of the two-pass FFT when the description leaves it open
+// (measured fastest): 128 up to 2^15 channels (whole 128-byte int8 rows per
+// column tile), 256 above.
+constexpr long long default_split(long long N) { return N <= (1LL << 15) ? 128 : 256; }
+
+// Splits that keep a precision's accuracy (the autotuner's candidates): rows
+// no longer than the default split's, since the rounding of a strong tone's
+// row grows with the row FFT's length; any split where the rows run in FP64
+// (FP32 plans from 2^18 channels).  precision: a pfbs_precision value.
+constexpr bool split_keeps_accuracy(long long N, int precision, long long n2) {
+    return n2 >= default_split(N) || (precision == 0 && fp32_row_precision(N) == kRowF64);
+}
+
 // LDS words allocated per column of an L-point sub-FFT plane: one pad word
 // per 16 elements and one more per column (the larger of the two layouts the
 // kernels use; pads of 0, 3 and 9 words per column measured no better).
@@ -173,6 +186,9 @@ extern thread_local LaunchEvents g_launch_events;
 
 // Set the calling thread's pfbs_last_error text and return st (plan.cpp).
 pfbs_status record_error(pfbs_status st, const char *msg);
+// The checks of pfbs_plan_create_ex on a description, leaving the calling
+// thread's pfbs_last_error text as it was (plan.cpp).
+pfbs_status validate_desc_quiet(const pfbs_plan_desc *d);
 
 // ---- autotune cache (autotune.cpp) ----
 // Fill *out from the newest cache line matching desc's shape on the current
@@ -192,6 +208,11 @@ hipError_t launch_tables_tw4(float2 *tw4, long long N1, long long N2, hipStream_
 hipError_t launch_front(const FrontArgs &a, int npol, bool pfb, bool single, int prec, int n_items,
                         hipStream_t s);
 hipError_t launch_back(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s);
+// the row pass by arithmetic (k_rows_f32.hip: 0 and kRowF64; k_rows_mfma.hip: 1 and 2)
+hipError_t launch_back_vector(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s);
+hipError_t launch_back_mfma(const BackArgs &a, int npol, int prec, int n_chunks, hipStream_t s);
+hipError_t init_back_vector(int lds_limit);
+hipError_t init_back_mfma(int lds_limit);
 hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s);
 // In place on n_dumps rows of [n_prod][N]: products -> Stokes, and/or the
 // shifted channel order.

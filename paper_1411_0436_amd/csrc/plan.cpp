@@ -237,6 +237,11 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
             return fail(PFBS_ERR_INVALID, "split_n2=%lld invalid for N=%lld (column length 64..512, "
                         "row length 32..4096)", (long long)d->split_n2, (long long)d->N);
     }
+    if (d->row_tile != 0 && d->N > kMaxSinglePass) {
+        const int64_t n2 = d->split_n2 ? d->split_n2 : default_split(d->N), n1 = d->N / n2;
+        if (d->row_tile < n1 || n2 % (d->row_tile / n1) != 0)
+            return fail(PFBS_ERR_INVALID, "row_tile=%d invalid for rows of %lld points", d->row_tile, (long long)n1);
+    }
     if (d->group_bytes < 0) return fail(PFBS_ERR_INVALID, "group_bytes < 0");
     if (d->col_run < 0 || d->col_run > 64) return fail(PFBS_ERR_INVALID, "col_run=%d out of [0, 64]", d->col_run);
     if (d->stream_z != 0 && d->stream_z != 1) return fail(PFBS_ERR_INVALID, "stream_z must be 0 or 1");
@@ -248,6 +253,8 @@ pfbs_status validate_desc(const pfbs_plan_desc *d) {
     if (d->tune < 0 || d->tune > 2) return fail(PFBS_ERR_INVALID, "tune must be 0, 1 or 2");
     if (d->tap_unroll < 0 || d->tap_unroll > 2) return fail(PFBS_ERR_INVALID, "tap_unroll must be 0, 1 or 2");
     if (d->col_pair < 0 || d->col_pair > 2) return fail(PFBS_ERR_INVALID, "col_pair must be 0, 1 or 2");
+    if (d->row_tile != 0 && d->row_tile != 1024 && d->row_tile != 2048 && d->row_tile != 4096)
+        return fail(PFBS_ERR_INVALID, "row_tile=%d: 0, 1024, 2048 or 4096", d->row_tile);
     return PFBS_OK;
 }
 
@@ -420,13 +427,10 @@ pfbs_status pfbs_plan_create_ex(pfbs_plan **out, const pfbs_plan_desc *desc_in) 
     p->nprod = p->npol == 2 ? 4 : 1;
     p->fourstep = p->N > kMaxSinglePass;
     if (p->fourstep) {
-        // Column length (measured fastest): 128 up to 2^15 channels (whole
-        // 128-byte int8 rows per column tile), 256 above.
-        const int64_t n2 = p->N <= (int64_t(1) << 15) ? 128 : 256;
-        p->N2 = desc->split_n2 ? desc->split_n2 : n2;
+        p->N2 = desc->split_n2 ? desc->split_n2 : default_split(p->N);
         p->N1 = p->N / p->N2;
         p->gA = make_geo((int)p->N2);
-        p->gB = make_geo((int)p->N1, back_tile(p->N1));
+        p->gB = make_geo((int)p->N1, desc->row_tile ? desc->row_tile : back_tile(p->N1));
         p->ntilesA = (int)(p->N1 / p->gA.T);
         p->ntilesB = (int)(p->N2 / p->gB.T);
     } else {
@@ -577,6 +581,7 @@ pfbs_status pfbs_plan_get_info(const pfbs_plan *p, pfbs_plan_info *info) {
     info->dumps_done = p->dumps_done;
     info->device_bytes = p->device_bytes;
     info->row_arith = p->fourstep ? p->prec_back : -1;
+    info->row_tile = p->fourstep ? p->gB.T * p->gB.L : 0;
     return PFBS_OK;
 }
 
@@ -1318,3 +1323,14 @@ pfbs_plan *pfbs_batch_plan(pfbs_batch *b, int32_t i) {
 }
 
 }  // extern "C"
+
+namespace pfbs {
+
+pfbs_status validate_desc_quiet(const pfbs_plan_desc *d) {
+    const std::string keep = g_err;
+    const pfbs_status st = validate_desc(d);
+    g_err = keep;
+    return st;
+}
+
+}  // namespace pfbs

@@ -50,7 +50,7 @@ class PlanDesc(ctypes.Structure):
         ("split_n2", ctypes.c_int64), ("group_bytes", ctypes.c_int64),
         ("col_run", ctypes.c_int32), ("stream_z", ctypes.c_int32),
         ("output", ctypes.c_int32), ("fftshift", ctypes.c_int32),
-        ("tap_unroll", ctypes.c_int32), ("col_pair", ctypes.c_int32),
+        ("tap_unroll", ctypes.c_int32), ("col_pair", ctypes.c_int32), ("row_tile", ctypes.c_int32),
     ]
 
 
@@ -61,7 +61,7 @@ class PlanInfo(ctypes.Structure):
         ("chunk", ctypes.c_int32), ("n_int", ctypes.c_int64), ("split_n1", ctypes.c_int64),
         ("split_n2", ctypes.c_int64), ("frames_seen", ctypes.c_int64),
         ("spectra_done", ctypes.c_int64), ("dumps_done", ctypes.c_int64),
-        ("device_bytes", ctypes.c_int64), ("row_arith", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("device_bytes", ctypes.c_int64), ("row_arith", ctypes.c_int32), ("row_tile", ctypes.c_int32),
     ]
 
 
@@ -157,7 +157,7 @@ def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_P
               n_int: int = 1, precision: int = PREC_FP32, device: int = -1, custom_taps=None,
               tune: int = 0, chunk: int = 0, split_n2: int = 0, group_bytes: int = 0,
               col_run: int = 0, stream_z: int = 0, output: int = 0, fftshift: int = 0,
-              tap_unroll: int = 0, col_pair: int = 0):
+              tap_unroll: int = 0, col_pair: int = 0, row_tile: int = 0):
     """A PlanDesc; ``custom_taps`` (float64 numpy array) is kept alive on the
     returned object until the plan is created."""
     import numpy as np
@@ -165,7 +165,7 @@ def make_desc(N: int, P: int, window: int = WINDOW_HANN_SINC, mode: int = MODE_P
                  precision=precision, device=device, custom_taps=None, tune=tune,
                  chunk=chunk, split_n2=split_n2, group_bytes=group_bytes,
                  col_run=col_run, stream_z=stream_z, output=output, fftshift=fftshift,
-                 tap_unroll=tap_unroll, col_pair=col_pair)
+                 tap_unroll=tap_unroll, col_pair=col_pair, row_tile=row_tile)
     keep = None
     if custom_taps is not None:
         keep = np.ascontiguousarray(custom_taps, dtype=np.float64)
@@ -185,7 +185,7 @@ def autotune(block_samples: int = 0, max_candidates: int = 0, **desc_kw):
     sps = ctypes.c_double(0.0)
     _check(L.pfbs_autotune(ctypes.byref(d), block_samples, max_candidates, ctypes.byref(best),
                            ctypes.byref(sps)))
-    fields = ("split_n2", "chunk", "col_run", "stream_z", "tap_unroll", "col_pair")
+    fields = ("split_n2", "chunk", "col_run", "stream_z", "tap_unroll", "col_pair", "row_tile")
     return {f: getattr(best, f) for f in fields}, sps.value
 
 

@@ -21,16 +21,20 @@ def test_autotune_returns_valid_setting_and_caches_it(tmp_path, monkeypatch):
     N = 8192
     fields, sps = pf.autotune(block_samples=64 * N, max_candidates=8, N=N, P=8, n_pol=2, n_int=16)
     assert sps > 0
-    assert fields["split_n2"] in (64, 128, 256, 512)
-    assert fields["chunk"] in (8, 16, 32, 64)
+    assert fields["split_n2"] in (128, 256, 512)  # rows no longer than the default split's
+    assert fields["chunk"] in (0, 4, 8, 16, 32, 64)
+    assert fields["row_tile"] in (0, 2048, 4096)
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     f = lines[0].split()
-    assert f[0] == "pfbs-tune-v3" and f[1] == "gfx950" and "pfbspec " + f[2] == pf.version()
+    assert f[0] == "pfbs-tune-v4" and f[1] == "gfx950" and "pfbspec " + f[2] == pf.version()
+    assert len(f) == 18
     assert f[3:9] == ["8192", "8", "0", "2", "16", "0"]
     plan = pf.Plan(N, 8, n_pol=2, n_int=16, tune=1)
     info = plan.info()
-    assert info["split_n2"] == fields["split_n2"] and info["chunk"] == fields["chunk"]
+    assert info["split_n2"] == fields["split_n2"]
+    assert fields["chunk"] == 0 or info["chunk"] == fields["chunk"]
+    assert info["row_tile"] == (fields["row_tile"] or 1024)
     x = synth.generate(synth.noise_only(2, 20.0, 77), 0, 60 * N)
     dumps, _, _ = run_stream(plan, x, [23, 37])
     ref = oracle.dumps(x, N, 8, oracle.taps(N, 8), False, 16)
@@ -74,3 +78,33 @@ def test_tuned_fp32_largest_mode_stays_within_1e5(tmp_path, monkeypatch):
     plan.close()
     ref = oracle.integrate(x, N, 8, oracle.taps(N, 8), False, 0, 64, synth.default_workers())
     assert rel_err(dumps[0], ref).max() <= 1e-5
+
+
+def test_tuner_full_search_and_row_tiles_give_same_bits(tmp_path, monkeypatch):
+    """A full coordinate search on a 2^17-channel MIXED shape (every field),
+    and plans that differ only in the row-pass tile width (1024, 2048 and
+    4096 points: 2, 4 and 8 rows of 512 per workgroup step) and in the column
+    kernel's form (one or two spectra per workgroup) give the same dumps bit
+    for bit."""
+    require_gpu()
+    monkeypatch.delenv("PFBS_TUNE_CACHE", raising=False)
+    N = 1 << 17
+    fields, sps = pf.autotune(block_samples=16 * N, N=N, P=8, n_pol=2, n_int=3, precision=pf.PREC_MIXED)
+    assert sps > 0 and fields["split_n2"] in (256, 512) and fields["col_pair"] in (0, 1, 2)
+    x = synth.generate(synth.spec_subband(6, N), 5, 25 * N)
+    ref = None
+    for rt in (0, 2048, 4096):
+        for cp in (1, 2):
+            plan = pf.Plan(N, 8, n_pol=2, n_int=3, precision=pf.PREC_MIXED, split_n2=256, row_tile=rt, col_pair=cp)
+            assert plan.info()["row_tile"] == (rt or 1024)
+            d, _, _ = run_stream(plan, x, [9, 16])
+            plan.close()
+            if ref is None:
+                ref = d
+            assert d.shape == ref.shape and np.array_equal(d, ref), (rt, cp)
+
+
+def test_row_tile_rejected_when_shorter_than_rows():
+    require_gpu()
+    with pytest.raises(pf.PfbsError):
+        pf.Plan(1 << 19, 8, n_pol=2, n_int=4, split_n2=128, row_tile=2048)   # rows of 4096
