@@ -2,7 +2,7 @@
 // watch a program without an interpreter in between (hardware counters), and
 // as an example of the boundary used from C/C++.
 //
-//   pfbs_run N P mode n_pol n_int block_samples blocks steps [precision [split_n2 [chunk]]]
+//   pfbs_run N P mode n_pol n_int block_samples blocks steps [precision [split_n2 [chunk [col_pair]]]]
 //       mode 0 = PFB (Hann-windowed sinc), 1 = direct.  Allocates `blocks`
 //       device blocks of block_samples time samples filled with seeded
 //       pseudo-random int8 values, runs one untimed pass and then `steps`
@@ -57,7 +57,8 @@ static int run_copy(long long mib) {
 int main(int argc, char **argv) {
     if (argc == 3 && strcmp(argv[1], "--copy") == 0) return run_copy(atoll(argv[2]));
     if (argc < 9) {
-        fprintf(stderr, "usage: %s N P mode n_pol n_int block_samples blocks steps [precision [split_n2 [chunk]]]\n"
+        fprintf(stderr, "usage: %s N P mode n_pol n_int block_samples blocks steps "
+                        "[precision [split_n2 [chunk [col_pair]]]]\n"
                         "       %s --copy MiB\n", argv[0], argv[0]);
         return 2;
     }
@@ -73,6 +74,7 @@ int main(int argc, char **argv) {
     d.precision = argc > 9 ? atoi(argv[9]) : 0;
     d.split_n2 = argc > 10 ? atoll(argv[10]) : 0;
     d.chunk = argc > 11 ? atoi(argv[11]) : 0;
+    d.col_pair = argc > 12 ? atoi(argv[12]) : 0;
     d.window = PFBS_WINDOW_HANN_SINC;
     d.device = -1;
     if (nblk < 1 || steps < 1 || B <= 0) {

@@ -7,6 +7,12 @@
         --workload W --precision P --command "..."
         SQ instruction / wait counters per dispatch and per wave;
 
+    python -m paper_1411_0436_amd.prof_summary compare OUT --match NAME --set LABEL=DIR[,DIR...]
+        --set LABEL=DIR[,DIR...] [--per-launch-units U] --command "..."
+        counters of the kernels whose name contains NAME under two or more
+        settings (each from one or more counter runs), side by side with their
+        ratio to the first, and per unit of work when U is given;
+
     python -m paper_1411_0436_amd.prof_summary traffic --fetch DIR --write DIR
         --copy-fetch DIR --copy-write DIR --match NAME --kind KIND
         --workload W --precision P OUT --command "..."
@@ -147,6 +153,42 @@ def cmd_sq(a):
     _write(a.out, out)
 
 
+def cmd_compare(a):
+    """Per-dispatch counters of the kernels whose name contains MATCH under
+    several labelled settings, with the ratio of each to the first setting."""
+    sets = []
+    for spec in a.set:
+        label, dirs = spec.split("=", 1)
+        vals, names = collections.OrderedDict(), set()
+        for d in dirs.split(","):
+            for r in _counter_rows(d):
+                if a.match not in r["Kernel_Name"]:
+                    continue
+                names.add(r["Kernel_Name"].replace("void ", "").split("(")[0])
+                vals.setdefault(r["Counter_Name"], collections.defaultdict(float))[r["Dispatch_Id"]] += \
+                    float(r["Counter_Value"])
+        sets.append((label, {k: sum(v.values()) / max(1, len(v)) for k, v in vals.items()}, sorted(names)))
+    out = ["# rocprofv3 counters per dispatch under several settings (summed over the counter's instances,",
+           "# averaged over dispatches)", "# commands: %s" % a.command, "# kernel sources sha1: %s" % kernel_digest(), ""]
+    for label, _, names in sets:
+        out.append("%s: %s" % (label, "; ".join(names)))
+    counters = sorted(set().union(*[set(v) for _, v, _ in sets]))
+    head = "%-30s" % "counter" + "".join("%16s" % lab for lab, _, _ in sets) + "".join(
+        "%14s" % ("%s/%s" % (lab[:6], sets[0][0][:6])) for lab, _, _ in sets[1:])
+    out += ["", head]
+    for c in counters:
+        v0 = sets[0][1].get(c)
+        row = "%-30s" % c + "".join("%16.4g" % v.get(c, float("nan")) for _, v, _ in sets)
+        row += "".join("%14.3f" % (v.get(c, float("nan")) / v0 if v0 else float("nan")) for _, v, _ in sets[1:])
+        out.append(row)
+    if a.per_launch_units:
+        out += ["", "per unit of work (%g units per launch):" % a.per_launch_units]
+        for c in counters:
+            out.append("%-30s" % c + "".join("%16.4g" % (v.get(c, float("nan")) / a.per_launch_units)
+                                              for _, v, _ in sets))
+    _write(a.out, out)
+
+
 def _write(path, lines):
     text = "\n".join(lines) + "\n"
     if path == "-":
@@ -182,8 +224,14 @@ def main(argv=None):
     q.add_argument("--workload", required=True)
     q.add_argument("--precision", default="fp32")
     q.add_argument("--command", required=True)
+    c = sub.add_parser("compare", help="counters under several settings")
+    c.add_argument("out")
+    c.add_argument("--match", required=True)
+    c.add_argument("--set", action="append", required=True, help="LABEL=DIR[,DIR...]")
+    c.add_argument("--per-launch-units", type=float, default=0.0)
+    c.add_argument("--command", required=True)
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "sq": cmd_sq}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "sq": cmd_sq, "compare": cmd_compare}[a.cmd](a)
 
 
 if __name__ == "__main__":
