@@ -23,6 +23,23 @@ __device__ __forceinline__ int find_entry(const E *t, int n, int bid) {
 template <int NPOL, int L>
 constexpr int front_lds_floats() { return 2 * NPOL * (kTilePoints / L) * lds_pitch(L); }
 
+// A single-pass entry: its body in the workgroup (or half) starting at smem
+// + half * (the body's LDS).
+template <int NPOL>
+__device__ __forceinline__ void single_entry(const FrontArgs &a, int vb, int tid, float *smem, int L, bool pfb,
+                                             int half) {
+#define PFBS_BF_SINGLE(LL)                                                                                \
+    if (L == LL) {                                                                                        \
+        float *lds = smem + half * front_lds_floats<NPOL, LL>();                                          \
+        if (pfb) front_single_body<NPOL, true, LL, 0, 0>(a, vb, tid, lds);                                \
+        else front_single_body<NPOL, false, LL, 0, 0>(a, vb, tid, lds);                                   \
+        return;                                                                                           \
+    }
+    PFBS_BF_SINGLE(16) PFBS_BF_SINGLE(32) PFBS_BF_SINGLE(64) PFBS_BF_SINGLE(128) PFBS_BF_SINGLE(256)
+    PFBS_BF_SINGLE(512) PFBS_BF_SINGLE(1024) PFBS_BF_SINGLE(2048) PFBS_BF_SINGLE(4096)
+#undef PFBS_BF_SINGLE
+}
+
 // Front phase.  A workgroup is twice the threads of a one-spectrum front
 // kernel: a two-spectra column entry uses it whole, exactly as its own
 // kernel; single-pass and one-spectrum column entries run two of their
@@ -34,7 +51,7 @@ constexpr int front_lds_floats() { return 2 * NPOL * (kTilePoints / L) * lds_pit
 // column tile, which share frames in its cache).  The halves synchronise
 // with workgroup barriers that both take part in; a half whose work ends
 // first exits, and a barrier then waits only for the waves still running.
-template <int NPOL>
+template <int NPOL, bool WITH_SINGLE>
 __global__ __launch_bounds__(2 * kTilePoints / 16 * NPOL, 4) void k_batch_front(const BatchFrontEntry *__restrict__ t,
                                                                            int n) {
     extern __shared__ float smem[];
@@ -66,24 +83,16 @@ __global__ __launch_bounds__(2 * kTilePoints / 16 * NPOL, 4) void k_batch_front(
     if (vb >= items) return;
     const int tid = (int)threadIdx.x - half * HALF;
     if (kind == 0) {
-#define PFBS_BF_SINGLE(LL)                                                                                \
-    if (L == LL) {                                                                                        \
-        float *lds = smem + half * front_lds_floats<NPOL, LL>();                                          \
-        if (pfb) front_single_body<NPOL, true, LL, 0, 0>(a, vb, tid, lds);                                \
-        else front_single_body<NPOL, false, LL, 0, 0>(a, vb, tid, lds);                                   \
-        return;                                                                                           \
-    }
-        PFBS_BF_SINGLE(16) PFBS_BF_SINGLE(32) PFBS_BF_SINGLE(64) PFBS_BF_SINGLE(128) PFBS_BF_SINGLE(256)
-        PFBS_BF_SINGLE(512) PFBS_BF_SINGLE(1024) PFBS_BF_SINGLE(2048) PFBS_BF_SINGLE(4096)
-#undef PFBS_BF_SINGLE
+        if constexpr (WITH_SINGLE) single_entry<NPOL>(a, vb, tid, smem, L, pfb, half);
         return;
     }
+    // one-spectrum column passes with the run-time tap loop: the same
+    // arithmetic in the same order as the compile-time loops, so the same
+    // bits, in fewer registers
 #define PFBS_BF_COLS(LL)                                                                                  \
     if (L == LL) {                                                                                        \
         float *lds = smem + half * front_lds_floats<NPOL, LL>();                                          \
         if (!pfb) front_cols_body<NPOL, false, LL, 0, 0>(a, vb, items, tid, lds);                         \
-        else if (pt == 4) front_cols_body<NPOL, true, LL, 0, 4>(a, vb, items, tid, lds);                  \
-        else if (pt == 8) front_cols_body<NPOL, true, LL, 0, 8>(a, vb, items, tid, lds);                  \
         else front_cols_body<NPOL, true, LL, 0, 0>(a, vb, items, tid, lds);                               \
         return;                                                                                           \
     }
@@ -116,9 +125,72 @@ __global__ __launch_bounds__(TP / 16 * NPOL) void k_batch_back(const BatchBackEn
 #undef PFBS_BB
 }
 
-const void *batch_front_fn(int npol) {
-    return npol == 2 ? reinterpret_cast<const void *>(&k_batch_front<2>)
-                     : reinterpret_cast<const void *>(&k_batch_front<1>);
+// Row phase with the single passes: 2048-point row tiles, two row-pass
+// workgroups per workgroup (one per half, as the front phase runs its
+// column passes), and single-pass entries on the whole workgroup, which has
+// exactly a single-pass kernel's threads.  The single passes need more than
+// the 128 registers of the front phase's 1024-thread workgroup; here they
+// run at the row pass's register budget, and the front phase keeps only
+// column passes.  The single passes come first in block order (each walks a
+// whole chunk of spectra, so they start before the shorter row workgroups),
+// then the row entries; the single-pass entries are in the front table.
+template <int NPOL>
+__global__ __launch_bounds__(2 * 2048 / 16 * NPOL) void k_batch_rows_single(const BatchBackEntry *__restrict__ tb,
+                                                                          int nb,
+                                                                          const BatchFrontEntry *__restrict__ ts,
+                                                                          int ns) {
+    extern __shared__ float smem[];
+    constexpr int TP = 2048;
+    static_assert(2 * TP == kTilePoints, "a single-pass workgroup is two row-pass workgroups");
+    const int singles_end = ns > 0 ? ts[ns - 1].wg0 + ts[ns - 1].wgn : 0;
+    if ((int)blockIdx.x < singles_end) {
+        const int e = find_entry(ts, ns, blockIdx.x);
+        const int lb = blockIdx.x - ts[e].wg0;
+        if (lb < 0 || lb >= ts[e].wgn || lb >= ts[e].items) return;
+        FrontArgs a = ts[e].a;
+        globalise(a);
+        single_entry<NPOL>(a, lb, threadIdx.x, smem, ts[e].L, ts[e].pfb != 0, 0);
+        return;
+    }
+    if (nb <= 0) return;
+    const int bid = (int)blockIdx.x - singles_end;
+    const int e = find_entry(tb, nb, bid);
+    const int lb = bid - tb[e].wg0;
+    if (lb < 0 || lb >= tb[e].wgn) return;
+    constexpr int HALF = TP / 16 * NPOL;
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >= HALF ? 1 : 0;
+    const int vb = ((lb >> 3) << 4) + (half << 3) + (lb & 7);
+    const int items = tb[e].items;
+    if (vb >= items) return;
+    const int tid = (int)threadIdx.x - half * HALF;
+    BackArgs a = tb[e].a;
+    globalise(a);
+    const int L = tb[e].L, prec = tb[e].prec;
+#define PFBS_BR(LL)                                                                                       \
+    if constexpr (LL <= TP) {                                                                             \
+        if (L == LL) {                                                                                    \
+            constexpr int HF = 2 * NPOL * (TP / LL) * lds_pitch(LL);                                      \
+            if (prec == 3) back_body<NPOL, LL, 3, TP>(a, vb, tid, smem + half * 2 * HF);                  \
+            else if (prec == 2) back_body<NPOL, LL, 2, TP>(a, vb, tid, smem + half * HF);                 \
+            else back_body<NPOL, LL, 0, TP>(a, vb, tid, smem + half * HF);                                \
+            return;                                                                                       \
+        }                                                                                                 \
+    }
+    PFBS_BR(32) PFBS_BR(64) PFBS_BR(128) PFBS_BR(256) PFBS_BR(512) PFBS_BR(1024) PFBS_BR(2048)
+#undef PFBS_BR
+}
+
+const void *batch_front_fn(int npol, bool with_single) {
+    if (with_single)
+        return npol == 2 ? reinterpret_cast<const void *>(&k_batch_front<2, true>)
+                         : reinterpret_cast<const void *>(&k_batch_front<1, true>);
+    return npol == 2 ? reinterpret_cast<const void *>(&k_batch_front<2, false>)
+                     : reinterpret_cast<const void *>(&k_batch_front<1, false>);
+}
+
+const void *batch_rows_single_fn(int npol) {
+    return npol == 2 ? reinterpret_cast<const void *>(&k_batch_rows_single<2>)
+                     : reinterpret_cast<const void *>(&k_batch_rows_single<1>);
 }
 
 const void *batch_back_fn(int npol, int tp) {
@@ -136,9 +208,9 @@ const void *batch_back_fn(int npol, int tp) {
 bool init_batch(int lds_limit) {
     bool ok = true;
     for (int npol = 1; npol <= 2; ++npol) {
-        if (hipFuncSetAttribute(batch_front_fn(npol), hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) !=
-            hipSuccess)
-            ok = false;
+        for (const void *f : {batch_front_fn(npol, false), batch_front_fn(npol, true), batch_rows_single_fn(npol)})
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess)
+                ok = false;
         for (int tp : {1024, 2048, 4096})
             if (hipFuncSetAttribute(batch_back_fn(npol, tp), hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) !=
                 hipSuccess)

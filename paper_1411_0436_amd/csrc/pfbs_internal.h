@@ -138,6 +138,7 @@ struct BatchBackEntry {
     int L;
     int prec;        // row arithmetic: 0 FP32, 2 split FP16 on the matrix cores, 3 FP64
     int wg0, wgn;
+    int items;       // the body's block count (row phase with single passes: two per workgroup)
     BackArgs a;
 };
 
@@ -154,8 +155,9 @@ struct BatchTailEntry {
 
 // Kernels of the batched launches (k_batch.hip, k_aux.hip): the front phase,
 // the row phase at tile size tp (1024, 2048 or 4096 points), the tail.
-const void *batch_front_fn(int npol);
+const void *batch_front_fn(int npol, bool with_single);
 const void *batch_back_fn(int npol, int tp);
+const void *batch_rows_single_fn(int npol);   // 2048-point row tiles + single passes
 // Compile-time tap count of the pre-filter kernels for P taps (0: taken from
 // the arguments at run time; also 0 without the filter or when not unrolled).
 constexpr int tap_variant(bool pfb, int P, bool unroll) { return unroll && pfb && (P == 4 || P == 8) ? P : 0; }

@@ -158,6 +158,7 @@ struct pfbs_batch {
     std::vector<pfbs_plan *> plans;
     int npol;
     int tpb;        // row-phase tile points per polarisation (1024, 2048 or 4096)
+    bool rows_single;  // single passes run in the row phase (2048-point row tiles)
     int launches;   // kernel launches made by the last execute
     // entry tables, a ring of kTabRing buffers: buffer k is filled on the
     // host, copied to the device on the batch's copy stream while the
@@ -1013,6 +1014,16 @@ struct BLaunch {
     size_t lds;
     const void *table;
     int n;
+    const void *table2;   // rows-and-single-passes kernel: the single-pass entries
+    int n2;
+    void *args[4];
+    void **set_args() {
+        args[0] = (void *)&table;
+        args[1] = (void *)&n;
+        args[2] = (void *)&table2;
+        args[3] = (void *)&n2;
+        return args;
+    }
 };
 
 // Upper bounds on the workgroups of one sub-band's launches for a block of F
@@ -1070,14 +1081,22 @@ pfbs_status pfbs_batch_create(pfbs_batch **out, const pfbs_plan_desc *descs, int
         b->plans.push_back(p);
         if (p->fourstep) b->tpb = std::max(b->tpb, back_tile((int)p->N1));
     }
+    bool has_single = false;
+    for (pfbs_plan *p : b->plans) has_single = has_single || !p->fourstep;
+    // single passes go to the row phase (2048-point row tiles, whose
+    // workgroup pair is one single-pass workgroup) unless a row is longer
+    b->rows_single = st == PFBS_OK && has_single && b->tpb <= 2048;
+    if (b->rows_single) b->tpb = 2048;
     if (st == PFBS_OK && !g_batch_ok[b->plans[0]->device])
         st = fail(PFBS_ERR_UNSUPPORTED, "the device refused the LDS size of the batched kernels");
     if (st == PFBS_OK) {
         // LDS of the two phase workgroups
         size_t lf = 0, lb = 0;
+        const size_t rows_mul = b->rows_single ? 2 : 1;   // two row workgroups per workgroup
         for (pfbs_plan *p : b->plans) {
-            lf = std::max(lf, 2 * front_lds_bytes(p->gA, p->npol));
-            if (p->fourstep) lb = std::max(lb, batch_back_lds(p, b->tpb));
+            if (!p->fourstep && b->rows_single) lb = std::max(lb, front_lds_bytes(p->gA, p->npol));
+            else lf = std::max(lf, 2 * front_lds_bytes(p->gA, p->npol));
+            if (p->fourstep) lb = std::max(lb, rows_mul * batch_back_lds(p, b->tpb));
         }
         if (lf > (size_t)kPairLds || lb > (size_t)kPairLds)
             st = fail(PFBS_ERR_UNSUPPORTED, "batched launches need %zu / %zu bytes of LDS (limit %d)", lf, lb,
@@ -1137,30 +1156,36 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
         reinterpret_cast<const BatchTailEntry *>(dbase + offsetof(pfbs_batch::Tables, tail));
     std::vector<BLaunch> L;
 
-    // ---- front phase: every sub-band's single pass or column pass.  Entries
-    // with the longest work per workgroup first (single passes walk a whole
-    // chunk of spectra), so that they start while the rest fill the machine.
+    // ---- front phase: every sub-band's column pass, and its single pass
+    // unless those run in the row phase.  Entries with the longest work per
+    // workgroup first (single passes walk a whole chunk of spectra), so that
+    // they start while the rest fill the machine.  Single passes that run in
+    // the row phase sit at the end of the front table.
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     auto kind_of = [&](int i) { return !b->plans[i]->fourstep ? 0 : (w[i].any && w[i].groups[0].fa.pair ? 2 : 1); };
+    auto rank = [&](int i) {
+        const int k = kind_of(i);
+        return k == 0 ? (b->rows_single ? 3 : 0) : (k == 2 ? 1 : 2);
+    };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        const int kx = kind_of(x), ky = kind_of(y);
-        const int rx = kx == 0 ? 0 : (kx == 2 ? 1 : 2), ry = ky == 0 ? 0 : (ky == 2 ? 1 : 2);
+        const int rx = rank(x), ry = rank(y);
         if (rx != ry) return rx < ry;
         return b->plans[x]->N > b->plans[y]->N;
     });
-    int nf = 0, wf = 0, wf_max = 0;
-    size_t lds_f = 0;
+    int nf = 0, wf = 0, wf_max = 0;   // front-phase entries
+    int ns = 0, ws = 0, ws_max = 0;   // single passes of the row phase
+    size_t lds_f = 0, lds_s = 0;
     for (int i : order) {
         pfbs_plan *p = b->plans[i];
         const int64_t F = n_samples[i] / p->N;
         const int kind = kind_of(i);
-        BatchFrontEntry &E = T.front[nf++];
+        const bool in_rows = kind == 0 && b->rows_single;
+        BatchFrontEntry &E = T.front[nf + ns];
         memset(&E, 0, sizeof E);
         E.kind = kind;
         E.pfb = p->pfb ? 1 : 0;
         E.L = (int)p->gA.L;
-        E.wg0 = wf;
         int64_t items_max;
         const int64_t ga = std::max(1, p->ga_force);
         if (kind == 0) {
@@ -1178,16 +1203,31 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             items_max = p->ntilesA * (((F + run - 1) / run + 7) / 8 * 8);
         }
         E.pt = w[i].any ? E.a.pt : 0;
-        E.wgn = w[i].any ? front_wg(kind, E.items) : 0;
-        wf += E.wgn;
-        wf_max += front_wg(kind, items_max);
-        lds_f = std::max(lds_f, 2 * front_lds_bytes(p->gA, p->npol));
+        if (in_rows) {
+            // one single-pass workgroup per chunk, a whole row-phase workgroup
+            E.wg0 = ws;
+            E.wgn = w[i].any ? E.items : 0;
+            ws += E.wgn;
+            ws_max += (int)items_max;
+            lds_s = std::max(lds_s, front_lds_bytes(p->gA, p->npol));
+            ++ns;
+        } else {
+            E.wg0 = wf;
+            E.wgn = w[i].any ? front_wg(kind, E.items) : 0;
+            wf += E.wgn;
+            wf_max += front_wg(kind, items_max);
+            lds_f = std::max(lds_f, 2 * front_lds_bytes(p->gA, p->npol));
+            ++nf;
+        }
     }
-    if (wf > 0 || use_graph)
-        L.push_back({batch_front_fn(b->npol), use_graph ? wf_max : wf, 2 * kTilePoints / 16 * b->npol, lds_f,
-                     d_front, nf});
+    const bool front_single = !b->rows_single && std::any_of(b->plans.begin(), b->plans.end(),
+                                                             [](const pfbs_plan *p) { return !p->fourstep; });
+    if (nf > 0 && (wf > 0 || use_graph))
+        L.push_back({batch_front_fn(b->npol, front_single), use_graph ? wf_max : wf, 2 * kTilePoints / 16 * b->npol,
+                     lds_f, d_front, nf, nullptr, 0});
 
     // ---- row phase: every four-step sub-band's row pass at one tile size
+    // (with the single passes: two row workgroups per workgroup)
     int nbk = 0, wb = 0, wb_max = 0;
     size_t lds_b = 0;
     for (int i : order) {
@@ -1200,19 +1240,34 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
         E.L = (int)p->N1;
         E.prec = p->prec_back;
         E.wg0 = wb;
+        int64_t items = 0;
         if (w[i].any) {
             E.a = w[i].groups[0].ba;
             E.a.ntiles = ntb;
             E.a.g.T = b->tpb / (int)p->N1;
-            E.wgn = w[i].groups[0].nc * ntb;
+            items = (int64_t)w[i].groups[0].nc * ntb;
+        }
+        E.items = (int)items;
+        const int64_t items_max = ntb * max_chunks(p, F);
+        if (b->rows_single) {
+            E.wgn = (int)((items + 15) / 16 * 8);
+            wb_max += (int)((items_max + 15) / 16 * 8);
+            lds_b = std::max(lds_b, 2 * batch_back_lds(p, b->tpb));
+        } else {
+            E.wgn = (int)items;
+            wb_max += (int)items_max;
+            lds_b = std::max(lds_b, batch_back_lds(p, b->tpb));
         }
         wb += E.wgn;
-        wb_max += (int)(ntb * max_chunks(p, F));
-        lds_b = std::max(lds_b, batch_back_lds(p, b->tpb));
     }
-    if (nbk > 0 && (wb > 0 || use_graph))
+    if (b->rows_single) {
+        if (wb + ws > 0 || use_graph)
+            L.push_back({batch_rows_single_fn(b->npol), use_graph ? wb_max + ws_max : wb + ws,
+                         2 * b->tpb / 16 * b->npol, std::max(lds_b, lds_s), d_back, nbk, d_front + nf, ns});
+    } else if (nbk > 0 && (wb > 0 || use_graph)) {
         L.push_back({batch_back_fn(b->npol, b->tpb), use_graph ? wb_max : wb, b->tpb / 16 * b->npol, lds_b, d_back,
-                     nbk});
+                     nbk, nullptr, 0});
+    }
 
     // ---- tail: dump reductions and history copies
     int ntl = 0, wt = 0, wt_max = 0;
@@ -1246,7 +1301,7 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             wt_max += H.wgn;
         }
     }
-    if (wt > 0 || use_graph) L.push_back({batch_tail_fn(), use_graph ? wt_max : wt, 256, 0, d_tail, ntl});
+    if (wt > 0 || use_graph) L.push_back({batch_tail_fn(), use_graph ? wt_max : wt, 256, 0, d_tail, ntl, nullptr, 0});
 
     hipStream_t cs = (hipStream_t)stream;
     PFBS_HIP(p0, hipSetDevice(p0->device));
@@ -1259,10 +1314,9 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
     PFBS_HIP(p0, hipStreamWaitEvent(cs, b->copied[k], 0));
     b->launches = 0;
     if (!use_graph) {
-        for (const BLaunch &x : L) {
+        for (BLaunch &x : L) {
             if (x.grid <= 0) continue;
-            void *args[] = {(void *)&x.table, (void *)&x.n};
-            PFBS_HIP(p0, hipLaunchKernel(x.fn, dim3(x.grid), dim3(x.threads), args, x.lds, cs));
+            PFBS_HIP(p0, hipLaunchKernel(x.fn, dim3(x.grid), dim3(x.threads), x.set_args(), x.lds, cs));
             ++b->launches;
         }
     } else {
@@ -1270,10 +1324,9 @@ pfbs_status pfbs_batch_execute(pfbs_batch *b, const void *const *d_blocks, const
             hipStream_t s = b->gstream;
             PFBS_HIP(p0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             hipError_t le = hipSuccess;
-            for (const BLaunch &x : L) {
-                void *args[] = {(void *)&x.table, (void *)&x.n};
+            for (BLaunch &x : L) {
                 if (le == hipSuccess)
-                    le = hipLaunchKernel(x.fn, dim3(x.grid > 0 ? x.grid : 1), dim3(x.threads), args, x.lds, s);
+                    le = hipLaunchKernel(x.fn, dim3(x.grid > 0 ? x.grid : 1), dim3(x.threads), x.set_args(), x.lds, s);
             }
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(s, &g);

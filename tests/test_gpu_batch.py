@@ -191,8 +191,9 @@ def test_mixed_precision_batch_bitwise(use_graph):
         assert g.shape == want.shape and np.array_equal(g, want), i
 
 
-def test_batch_of_single_pass_sub_bands_only_has_no_row_phase():
-    """Only single-pass sub-bands: the front phase and the tail, two launches."""
+def test_batch_of_single_pass_sub_bands_only_has_two_launches():
+    """Only single-pass sub-bands: the single passes (in the row-phase
+    kernel, which has a single-pass workgroup's threads) and the tail."""
     torch = require_gpu()
     subs = [(256, 4, pf.MODE_PFB, 16), (4096, 1, pf.MODE_DIRECT, 8)]
     xs = [synth.generate(synth.spec_subband(s, N), 2, 1 << 17) for s, (N, *_r) in enumerate(subs)]
@@ -206,3 +207,29 @@ def test_batch_of_single_pass_sub_bands_only_has_no_row_phase():
     for i, (N, P, m, ni) in enumerate(subs):
         want, _p, _c = run_stream(pf.Plan(N, P, mode=m, n_pol=2, n_int=ni), xs[i], [(1 << 17) // N])
         assert np.array_equal(got[i], want), i
+
+
+def test_single_passes_beside_4096_point_rows_bitwise():
+    """A batch whose rows are 4096 points long (N = 2^20) keeps its single
+    passes in the front phase (the row phase's 4096-point tiles have twice a
+    single-pass workgroup's threads); dumps equal per-sub-band plans."""
+    torch = require_gpu()
+    subs = [(1024, 8, pf.MODE_PFB, 64), (1 << 20, 4, pf.MODE_PFB, 2)]
+    blk = 1 << 22
+    xs = [synth.generate(synth.spec_subband(s, N), 9, blk * 2) for s, (N, *_r) in enumerate(subs)]
+    b = pf.Batch([pf.make_desc(N=N, P=P, mode=m, n_pol=2, n_int=ni) for (N, P, m, ni) in subs])
+    got = [[] for _ in subs]
+    for k in range(2):
+        blocks = [torch.from_numpy(np.ascontiguousarray(x[k * blk:(k + 1) * blk])).cuda() for x in xs]
+        dumps = [torch.empty((max(p.dumps_in(blk), 1), 4, p.N), dtype=torch.float32, device="cuda") for p in b.plans]
+        nd = b.execute(blocks, dumps)
+        assert b.launches == 3
+        torch.cuda.synchronize()
+        for i in range(len(subs)):
+            if nd[i]:
+                got[i].append(dumps[i][:nd[i]].cpu().numpy())
+    b.close()
+    for i, (N, P, m, ni) in enumerate(subs):
+        want, _p, _c = run_stream(pf.Plan(N, P, mode=m, n_pol=2, n_int=ni), xs[i], [blk // N])
+        g = np.concatenate(got[i])
+        assert g.shape == want.shape and np.array_equal(g, want), i
