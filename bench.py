@@ -65,7 +65,7 @@ PRECISIONS = {"fp32": 0, "fp16": 1, "fp16x2": 2, "mixed": 3}
 # Sources that define the spectrometer kernels: a traffic summary under
 # profiles/ applies only while their digest is unchanged.
 KERNEL_SOURCES = ["fft_common.h", "fft_bodies.h", "k_single.hip", "k_fourstep.hip", "k_rows.h",
-                  "k_rows_f32.hip", "k_rows_mfma.hip", "k_batch.hip", "pfbs_internal.h"]
+                  "k_rows_f32.hip", "k_rows_mfma.hip", "pfbs_internal.h"]
 
 
 def kernel_digest():

@@ -34,7 +34,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["fft_common.h", "fft_bodies.h", "k_single.hip", "k_fourstep.hip", "k_rows.h",
-                  "k_rows_f32.hip", "k_rows_mfma.hip", "k_batch.hip", "pfbs_internal.h"]
+                  "k_rows_f32.hip", "k_rows_mfma.hip", "pfbs_internal.h"]
 
 
 def kernel_digest() -> str:
