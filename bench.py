@@ -132,6 +132,45 @@ def step_flops_per_pol_sample(w):
     return 4 * P + 5 * np.log2(w["N"]) + (8 if w["n_pol"] == 2 else 4)
 
 
+MFMA_FP16_PEAK_TFLOPS = 2500.0   # dense FP16 matrix-core peak (no sparsity)
+
+
+def mfma_flops_per_pol_sample(kind, prec_name, w, N1, N2):
+    """Dense matrix-core flops per complex pol-sample of one kernel: every
+    radix-16 pass on the matrix cores runs 16x16x32 FP16 products (16384
+    flops each) on 16 butterflies (256 points): 2 per group with single FP16
+    (128 flops per point and pass), 6 with the hi/lo split (384).  MIXED:
+    FP32 column/single pass, split-FP16 rows."""
+    front = {"fp16": 128, "fp16x2": 384}.get(prec_name, 0)
+    back = {"fp16": 128, "fp16x2": 384, "mixed": 384}.get(prec_name, 0)
+    if kind == "single_pass":
+        return front * (int(np.log2(w["N"])) // 4)
+    if kind == "column_pass":
+        return front * (int(np.log2(N2)) // 4)
+    if kind == "row_pass":
+        return back * (int(np.log2(N1)) // 4)
+    return 0.0
+
+
+def hbm_probe_gbps(mib=1024, reps=5):
+    """Bandwidth of a plain device-to-device copy on this GPU (bytes read +
+    written per second), the practical HBM ceiling beside the 8 TB/s peak."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def alg_bytes_per_pol_sample(kind, w):
     """Algorithmic HBM bytes per complex pol-sample: the int8 input (2 B, read
     by the kernel that pre-filters) and the dumps (4 B per product and channel
@@ -380,9 +419,9 @@ def cpu_baseline(w, blocks, spectra, min_seconds=10.0):
 
 
 def first_dump_error(w, prec, dev_blocks, ref, **plan_kw):
-    """Max per-channel relative error (cross terms on the sqrt(XX*YY) scale)
-    of the stream's first dump from a fresh plan of precision `prec`,
-    against the oracle's `ref` [n_prod, N]."""
+    """Max and median per-channel relative error (cross terms on the
+    sqrt(XX*YY) scale) of the stream's first dump from a fresh plan of
+    precision `prec`, against the oracle's `ref` [n_prod, N]."""
     import torch
     from paper_1411_0436_amd import pfbspec as pf
     N = w["N"]
@@ -397,10 +436,12 @@ def first_dump_error(w, prec, dev_blocks, ref, **plan_kw):
     got = d[0].cpu().numpy().astype(np.float64)
     plan.close()
     if ref.shape[0] == 1:
-        return float(np.max(np.abs(got[0] - ref[0]) / ref[0]))
-    sc = np.sqrt(ref[0] * ref[1])
-    return float(max(np.max(np.abs(got[0] - ref[0]) / ref[0]), np.max(np.abs(got[1] - ref[1]) / ref[1]),
-                     np.max(np.abs(got[2] - ref[2]) / sc), np.max(np.abs(got[3] - ref[3]) / sc)))
+        e = np.abs(got[0] - ref[0]) / ref[0]
+    else:
+        sc = np.sqrt(ref[0] * ref[1])
+        e = np.concatenate([np.abs(got[0] - ref[0]) / ref[0], np.abs(got[1] - ref[1]) / ref[1],
+                            np.abs(got[2] - ref[2]) / sc, np.abs(got[3] - ref[3]) / sc])
+    return float(np.max(e)), float(np.median(e))
 
 
 KNOBS = ("split_n2", "chunk", "col_run", "stream_z", "tap_unroll", "col_pair", "row_tile")
@@ -446,14 +487,16 @@ def time_path(w, prec_name, dev_blocks, args, knobs):
     kt_all = plan.timing_read()
     dom = max(kt_all, key=lambda k: kt_all[k][0])
     plan.timing(True, kinds=[dom])
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event at every step boundary: the total and the median step
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         step()
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = ev[0].elapsed_time(ev[-1])
+    step_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
     kt = plan.timing_read()
     plan.timing(False)
     plan.close()
@@ -462,7 +505,8 @@ def time_path(w, prec_name, dev_blocks, args, knobs):
     dom_ms, dom_n = kt[dom]
     avg_ms = dom_ms / max(dom_n, 1)
     per_launch = samples_per_step * args.steps / max(dom_n, 1)
-    return {"value": value, "ms_per_step": ms / args.steps, "info": info, "dominant": dom,
+    return {"value": value, "ms_per_step": ms / args.steps, "ms_per_step_median": step_ms[len(step_ms) // 2],
+            "info": info, "dominant": dom,
             "dom_avg_ms": avg_ms, "dom_pol_samples_per_launch": per_launch,
             "kernel_ms": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt_all.items() if v[1]},
             "kernel_launches_per_step": {k: v[1] // max(1, args.warmup) for k, v in kt_all.items() if v[1]}}
@@ -512,8 +556,8 @@ def bench_stream(args):
         r = time_path(w, p, dev_blocks, args, knobs)
         r["knobs"], r["tuned"] = knobs, tuned
         if ref is not None:
-            r["max_rel_err"] = first_dump_error(w, PRECISIONS[p], dev_blocks, ref,
-                                                group_bytes=args.group_mb << 20, **knobs)
+            r["max_rel_err"], r["median_rel_err"] = first_dump_error(w, PRECISIONS[p], dev_blocks, ref,
+                                                                     group_bytes=args.group_mb << 20, **knobs)
         paths[p] = r
         print("bench: %s %.2f Gsamples/s%s, %s %s" % (p, r["value"], "" if ref is None else
                                                       ", first-dump error %.3g" % r["max_rel_err"],
@@ -537,6 +581,21 @@ def bench_stream(args):
     dumps_per_step = samples_per_step / n_pol / N / w["n_int"]
     step_bytes = 2.0 * samples_per_step + dumps_per_step * 4.0 * (4 if n_pol == 2 else 1) * N
     step_flops = step_flops_per_pol_sample(w) * samples_per_step
+    probe = hbm_probe_gbps()
+    # the matrix cores: dense flops of each kernel that uses them, against its
+    # own average launch time, and over the whole step
+    mfma = {}
+    step_mfma = 0.0
+    for kind, kms in r["kernel_ms"].items():
+        f = mfma_flops_per_pol_sample(kind, best, w, info["split_n1"], info["split_n2"])
+        if f <= 0:
+            continue
+        launches = r["kernel_launches_per_step"][kind]
+        per_launch_samples = samples_per_step / max(launches, 1)
+        tf = f * per_launch_samples / (kms * 1e-3) / 1e12
+        mfma[kind] = {"dense_flops_per_pol_sample": f, "TFLOPs": round(tf, 1), "peak": MFMA_FP16_PEAK_TFLOPS,
+                      "frac": round(tf / MFMA_FP16_PEAK_TFLOPS, 4)}
+        step_mfma += f * samples_per_step
     out = {
         "metric": "Gsamples/s PFB+FFT+integrate (dual-pol) at N=32K..512K; MFMA vs FP32 at 1e-5",
         "value": round(value, 2),
@@ -545,6 +604,7 @@ def bench_stream(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_step"], 4),
+        "ms_per_step_median": round(r["ms_per_step_median"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -568,7 +628,9 @@ def bench_stream(args):
                      "avg_launch_ms": round(avg_ms, 5),
                      "flops_per_launch": round(fl),
                      "alg_bytes_per_launch": round(by),
-                     "hbm_GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBS, 4)},
+                     "hbm_GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBS, 4),
+                     "traffic_GBps": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1)},
+        "mfma_roofline": mfma or None,
         # the whole step against both roofs: method flops 4P + 5 log2 N + 8 per
         # pol-sample; algorithmic bytes = input + dumps
         "step_roofline": {"alg_flops_per_pol_sample": round(step_flops_per_pol_sample(w), 2),
@@ -576,11 +638,18 @@ def bench_stream(args):
                           "alu_frac": round(step_flops / step_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
                           "alg_bytes_per_step": round(step_bytes),
                           "hbm_GBps": round(step_bytes / step_s / 1e9, 1),
-                          "hbm_frac": round(step_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4)},
+                          "hbm_frac": round(step_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                          "hbm_probe_copy_GBps": round(probe, 1),
+                          "hbm_frac_of_probe": round(step_bytes / step_s / 1e9 / probe, 4),
+                          "mfma_TFLOPs": round(step_mfma / step_s / 1e12, 2),
+                          "mfma_frac": round(step_mfma / step_s / 1e12 / MFMA_FP16_PEAK_TFLOPS, 4)},
         "bandwidth_per_pol_GHz": round(value / n_pol, 3),
         "paper_style_Gbps": round(value / n_pol * 16, 1),
         "paths": {p: {"Gsamples_s": round(q["value"], 2), "ms_per_step": round(q["ms_per_step"], 4),
                       "max_rel_err_first_dump": None if "max_rel_err" not in q else float("%.3g" % q["max_rel_err"]),
+                      "median_rel_err_first_dump": None if "median_rel_err" not in q
+                      else float("%.3g" % q["median_rel_err"]),
+                      "ms_per_step_median": round(q["ms_per_step_median"], 4),
                       "within_1e-5": None if "max_rel_err" not in q else bool(q["max_rel_err"] <= 1e-5),
                       "split_n2": q["info"]["split_n2"], "row_arith": q["info"]["row_arith"],
                       "knobs": q["knobs"], "tuned": q["tuned"],
