@@ -318,7 +318,9 @@ pfbs_status pfbs_plan_timing_read(pfbs_plan *plan, double *ms, int64_t *launches
  * of device blocks of block_samples time samples (a positive multiple of N;
  * 0 = 2^24; as many distinct blocks as make at least 512 MB, at most 16, so
  * the input streams from HBM and not from the caches), timed with HIP events
- * around two passes over them.  Writes the fastest into *best (a copy of
+ * around three passes over them after one untimed pass (and the starting
+ * point run once, untimed, before any candidate is timed, so the device has
+ * settled).  Writes the fastest into *best (a copy of
  * *desc with those fields set and tune = 0) and its throughput in complex
  * samples per second into *best_samples_per_s (may be NULL).  At most
  * max_candidates settings are timed (0 = all).  If the environment variable

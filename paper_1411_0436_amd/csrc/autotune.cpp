@@ -237,13 +237,21 @@ extern "C" pfbs_status pfbs_autotune(const pfbs_plan_desc *desc, int64_t block_s
         pfbs_plan_desc v = c;
         if (pfbs::validate_desc_quiet(&v) != PFBS_OK) return;  // e.g. a row tile shorter than the rows
         ++timed_n;
-        const double t = time_candidate(&v, (const uint8_t *)d_block, nb, n, d_dumps, cap, s, 1, 2);
+        const double t = time_candidate(&v, (const uint8_t *)d_block, nb, n, d_dumps, cap, s, 1, 3);
         if (t > 0 && (best_t < 0 || t < best_t)) {
             best_t = t;
             winner = v;
         }
     };
     if (rs == PFBS_OK) {
+        // an untimed run of the starting point first: the device's clocks and
+        // caches settle before any candidate is compared, so that the first
+        // one timed is not the one that pays for it
+        {
+            pfbs_plan_desc v = base;
+            if (pfbs::validate_desc_quiet(&v) == PFBS_OK)
+                (void)time_candidate(&v, (const uint8_t *)d_block, nb, n, d_dumps, cap, s, 2, 1);
+        }
         try_cand(base);
         for (const Field &f : fields) {
             const pfbs_plan_desc cur = winner;

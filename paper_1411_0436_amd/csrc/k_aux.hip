@@ -162,6 +162,23 @@ __global__ __launch_bounds__(256) void k_history(uint4 *dst, Frames fr, long lon
     history_body(dst, fr, F, H, frame_vec, blockIdx.x, gridDim.x);
 }
 
+// A plan's tail in one launch: the dump reduction on the first blocks and the
+// tap-history copy on the rest (they touch disjoint buffers: the history is
+// written to the buffer the next block reads, the reduction reads partial
+// sums and writes dumps and carried sums).
+__global__ __launch_bounds__(256) void k_reduce_history(ReduceArgs a, int gx, int n_dumps, uint4 *hdst, Frames fr,
+                                                        long long F, int H, long long frame_vec, int n_hist) {
+    const int n_red = gx * n_dumps * a.n_prod;
+    const int b = blockIdx.x;
+    if (b < n_red) {
+        const int per_z = gx * n_dumps;
+        const int bz = b / per_z, rem = b - bz * per_z;
+        reduce_body(a, rem % gx, rem / gx, bz);
+    } else {
+        history_body(hdst, fr, F, H, frame_vec, b - n_red, n_hist);
+    }
+}
+
 // Batched tail: dump reductions and tap-history copies of every sub-band.
 __global__ __launch_bounds__(256) void k_batch_tail(const BatchTailEntry *__restrict__ t, int n) {
     if (n <= 0) return;
@@ -366,6 +383,18 @@ hipError_t launch_reduce(const ReduceArgs &a, int n_dumps, hipStream_t s) {
     if (a.N2 > 1) grid = dim3((unsigned)((a.N2 / kReduceTile) * (a.N1 / kReduceTile)), gy, (unsigned)a.n_prod);
     else grid = dim3((unsigned)((a.N + 255) / 256), gy, (unsigned)a.n_prod);
     PFBS_LAUNCH(k_reduce, grid, dim3(256), 0, s, a, n_dumps);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_history(const ReduceArgs &a, int n_dumps, uint8_t *dst, const Frames &fr, long long F,
+                                 int H, long long frame_bytes, hipStream_t s) {
+    const int gx = a.N2 > 1 ? (int)((a.N2 / kReduceTile) * (a.N1 / kReduceTile)) : (int)((a.N + 255) / 256);
+    const long long vec = frame_bytes / 16;
+    const int n_hist = grid_for(H * vec, 256);
+    const long long n_red = (long long)gx * std::max(n_dumps, 0) * a.n_prod;
+    if (n_red + n_hist > 0x7fffffffLL) return hipErrorInvalidValue;
+    PFBS_LAUNCH(k_reduce_history, dim3((unsigned)(n_red + n_hist)), dim3(256), 0, s, a, gx, std::max(n_dumps, 0),
+                reinterpret_cast<uint4 *>(dst), fr, F, H, vec, n_hist);
     return hipGetLastError();
 }
 

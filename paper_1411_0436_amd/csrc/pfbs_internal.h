@@ -222,6 +222,9 @@ hipError_t launch_dump_format(float *out, long long n_dumps, long long N, int n_
                               hipStream_t s);
 hipError_t launch_history(uint8_t *dst, const Frames &fr, long long F, int H, long long frame_bytes,
                           hipStream_t s);
+// launch_reduce and launch_history as one launch
+hipError_t launch_reduce_history(const ReduceArgs &a, int n_dumps, uint8_t *dst, const Frames &fr, long long F,
+                                 int H, long long frame_bytes, hipStream_t s);
 hipError_t launch_debug_pfb(float *y, const Frames &fr, const float *taps, long long N, int P,
                             int npol, bool pfb, long long j_lo, long long j_hi, hipStream_t s);
 hipError_t kernels_init();   // raise LDS limits once per process/device

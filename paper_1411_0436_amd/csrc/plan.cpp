@@ -807,13 +807,20 @@ pfbs_status launch_prepared(pfbs_plan *p, const Prepared &w, hipStream_t s, bool
                 PFBS_HIP(p, timed(p, 2, s, [&] { return launch_back(g.ba, p->npol, p->prec_back, g.nc, s); }));
             }
         }
-        PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(w.ra, w.n_dumps, s); }));
+        // the dump reduction and the tap-history copy share one launch
+        if (w.hist)
+            PFBS_HIP(p, timed(p, 3, s, [&] {
+                return launch_reduce_history(w.ra, w.n_dumps, p->hist[p->hcur ^ 1], w.fr, w.F, p->P - 1,
+                                             p->frame_bytes, s);
+            }));
+        else
+            PFBS_HIP(p, timed(p, 3, s, [&] { return launch_reduce(w.ra, w.n_dumps, s); }));
         if ((p->out_stokes || p->out_shift) && w.nd_out > 0)
             PFBS_HIP(p, timed(p, 3, s, [&] {
                 return launch_dump_format(w.ra.out, w.nd_out, p->N, p->nprod, p->out_stokes, p->out_shift, s);
             }));
     }
-    if (w.hist) {
+    if (w.hist && !w.any) {
         PFBS_HIP(p, timed(p, 4, s, [&] { return launch_history(p->hist[p->hcur ^ 1], w.fr, w.F, p->P - 1, p->frame_bytes, s); }));
     }
     return PFBS_OK;

@@ -244,3 +244,23 @@ def test_execute_rejects_bad_blocks():
     raw = torch.zeros(1024 * 8 * 4 + 16, dtype=torch.int8, device="cuda")
     with pytest.raises(pf.PfbsError):
         plan.execute(raw[1:1 + 1024 * 8 * 4])   # misaligned
+
+
+def test_plan_execute_is_three_launches_with_the_history_in_the_reduction():
+    """A two-pass PFB plan's block is three launches: the column pass, the row
+    pass, and one launch holding the dump reduction and the tap-history copy
+    (the history copy has no launch of its own once spectra complete)."""
+    N, P, frames = 32768, 8, [12, 9]
+    x = synth.generate(tone_stream(2, N, 5), 0, N * sum(frames))
+    plan = _plan(N, P, pf.MODE_PFB, 2, 4)
+    plan.timing(True)
+    d_split, _, _ = run_stream(plan, x, frames)
+    kt = plan.timing_read()
+    plan.close()
+    assert kt["column_pass"][1] == kt["row_pass"][1] == kt["dump_reduce"][1] == len(frames)
+    assert kt["tap_history"][1] == 0
+    # the history copied in the first block's reduction launch feeds the second
+    ref = oracle.dumps(x, N, P, oracle.taps(N, P), False, 4)
+    assert d_split.shape == ref.shape
+    for d in range(ref.shape[0]):
+        assert within_fp32_bound(d_split[d], ref[d], N, n2=128) <= 1.0

@@ -1,5 +1,6 @@
 """Kernel timing through the dispatch timestamps: every launch of a timed
-block is counted under its kind, the durations are positive and add up to
+block is counted under its kind (the history copy inside the reduction's
+launch), the durations are positive and add up to
 no more than the wall time of the same work, and timing changes no result."""
 import numpy as np
 import pytest
@@ -11,8 +12,10 @@ from tests.gpu_util import require_gpu
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("N,kinds", [(1024, ("single_pass", "dump_reduce", "tap_history")),
-                                     (32768, ("column_pass", "row_pass", "dump_reduce", "tap_history"))])
+# the tap-history copy rides in the dump reduction's launch (kind dump_reduce)
+# whenever a block completes spectra, as these do
+@pytest.mark.parametrize("N,kinds", [(1024, ("single_pass", "dump_reduce")),
+                                     (32768, ("column_pass", "row_pass", "dump_reduce"))])
 def test_timing_counts_every_launch(N, kinds):
     torch = require_gpu()
     x = synth.generate(synth.spec_c2(n_ref=N), 0, 40 * N)
@@ -34,5 +37,6 @@ def test_timing_counts_every_launch(N, kinds):
     for k in kinds:
         ms, cnt = t[k]
         assert cnt >= 1 and ms > 0, (k, t)
+    assert t["tap_history"][1] == 0, t
     assert sum(ms for ms, cnt in t.values()) <= wall * 1.05 + 0.01
     assert b.timing_read()["dump_reduce"] == (0.0, 0)  # read once, then forgotten
