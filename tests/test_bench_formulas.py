@@ -50,3 +50,16 @@ def test_matrix_core_flops_of_the_split_fp16_passes():
     assert bench.mfma_flops_per_pol_sample("column_pass", "fp16x2", w, 2048, 256) == 768
     assert bench.mfma_flops_per_pol_sample("row_pass", "fp16", w, 2048, 256) == 2 * 2 * 16384 / 256
     assert bench.mfma_flops_per_pol_sample("row_pass", "fp32", w, 2048, 256) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The spectrometer runs on one GPU; asked for several, the benchmark
+    exits with status 2 and says why, before touching any device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and r.stdout == ""
+    assert "one GPU" in r.stderr and "--gpus 2" in r.stderr
