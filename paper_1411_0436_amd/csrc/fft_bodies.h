@@ -538,6 +538,21 @@ template <int L, int PREC> struct BackPad {
     static constexpr int PS = ((PREC == 0 || PREC == 3) && L >= 512) ? 4 : 5;
 };
 
+// The row kernels loop over the spectra of a chunk with the same lane
+// indices in every iteration, and the compiler hoists every LDS offset derived
+// from them out of the loop, holding them in registers for the whole kernel.
+// For the matrix-core and FP64 rows the lane index is passed through an empty
+// asm statement at each iteration, so the offsets are recomputed per spectrum
+// instead (the split-FP16 kernel on 2048-point rows: 224 -> 125 VGPRs, two ->
+// four waves per SIMD, row pass -5 %); the FP32 rows, whose registers go to
+// the next spectrum's prefetched intermediate, measured faster with them
+// hoisted.
+template <int PREC> struct FreshIdx { static constexpr bool value = PREC != 0; };
+__device__ __forceinline__ int opaque_int(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // PREC 3: the row FFT and the products in FP64 on the vector ALUs (each
 // product rounded once to FP32 before it is accumulated); the intermediate
 // stays FP32.  A strong tone's energy sits in one intermediate row, and an
@@ -609,6 +624,10 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid, int tid, f
     }
 
     for (long long j = js; j < je; ++j) {
+        // lane indices of this spectrum's iteration (see FreshIdx)
+        const int tj = FreshIdx<PREC>::value ? opaque_int(tid) : tid;
+        const int pol_j = tj / G::TPP, lt_j = tj % G::TPP;
+        const int c_j = lt_j >> (G::logL - 4), bb_j = lt_j & (G::L16 - 1);
         const float2 *zb = a.Z + (j - a.jz0) * NPOL * N + (long long)k2_0 * L;
         if constexpr (ZPRE) {
             z_to_lds(zc);
@@ -616,7 +635,7 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid, int tid, f
             // two consecutive n1 (16 bytes) per access
 #pragma unroll
             for (int s = 0; s < (NPOL * G::TP) / (2 * NB); ++s) {
-                const int i = tid + NB * s;
+                const int i = tj + NB * s;
                 const int n1 = 2 * (i & (L / 2 - 1));
                 const int cc = (i >> (G::logL - 1)) & (G::T - 1);
                 const int pp = i >> (G::logL - 1 + G::logT);
@@ -634,13 +653,13 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid, int tid, f
             if (j + 1 < je) z_loads(j + 1, zc);
         }
         C v[16];
-        if constexpr (F64) fft_plane<G, FftWave<G, PREC>::value, double>(sre, sim, pol, lt, a.g.tw64, v);
-        else fft_plane_p<G, PREC>(sre, sim, pol, lt, a.g.tw, Wm, v, NPOL == 1);
+        if constexpr (F64) fft_plane<G, FftWave<G, PREC>::value, double>(sre, sim, pol_j, lt_j, a.g.tw64, v);
+        else fft_plane_p<G, PREC>(sre, sim, pol_j, lt_j, a.g.tw, Wm, v, NPOL == 1);
         if constexpr (NPOL == 2) {
             if constexpr (!FftPrec<PREC>::IN_LDS) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int ad = G::idx(pol, c_own, bb_own + r * G::L16);
+                    const int ad = G::idx(pol_j, c_j, bb_j + r * G::L16);
                     sre[ad] = v[r].x;
                     sim[ad] = v[r].y;
                 }
@@ -648,7 +667,7 @@ __device__ __forceinline__ void back_body(const BackArgs &a, int bid, int tid, f
             }
 #pragma unroll
             for (int i = 0; i < BINS; ++i) {
-                const int e = tid + NB * i;
+                const int e = tj + NB * i;
                 const int c = e >> G::logL, k = e & (L - 1);
                 const int ax = G::idx(0, c, k), ay = G::idx(1, c, k);
                 prod4(acc[i], Cx<C>::mk(sre[ax], sim[ax]), Cx<C>::mk(sre[ay], sim[ay]));
