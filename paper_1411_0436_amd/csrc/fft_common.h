@@ -192,7 +192,7 @@ struct Geom {
     static_assert((PS == 4 || PS == 5) && Lp <= lds_pitch(L), "LDS padding within the host's LDS size");
     // every column is transformed by lanes of a single wave
     static constexpr bool WAVE_COLS = L16 <= 64 && TPP % 64 == 0;
-    __device__ __forceinline__ static int idx(int pol, int c, int e) {
+    __host__ __device__ __forceinline__ static constexpr int idx(int pol, int c, int e) {
         return (pol * T + c) * Lp + e + (e >> PS);
     }
     // Offset of radix-16 pass i in the twiddle table (Ns = r0 * 16^i entries each of 15).
@@ -386,6 +386,62 @@ __device__ __forceinline__ MfmaW mfma_operands_load(const uint4 *t, int lane) {
     return w;
 }
 
+// LDS positions and twiddle rows of matrix-core pass I as functions of the
+// wave, the lane, the group g of 16 butterflies and the point t read or the
+// output i written: the expressions of pass16_mfma.  Where every lane of every
+// wave sees the same differences from its (g, t) = (0, 0) position as lane 0
+// of wave 0 (checked exhaustively at compile time: LINEAR), the pass computes
+// one position per lane and adds those differences as compile-time offsets,
+// so each LDS access uses the instruction's offset field instead of an address
+// register of its own.
+template <class G, int I> struct Mfma16Pos {
+    static constexpr int Ns = G::r0 * (1 << (4 * I));
+    static constexpr int rd(int wv, int lane, int g, int t) {
+        const int n = lane & 15, kb = lane >> 4;
+        const int b = wv * 64 + g * 16 + n;
+        const int c = b >> (G::logL - 4), bb = b & (G::L16 - 1);
+        return G::idx(0, c, bb + (4 * kb + t) * G::L16);
+    }
+    static constexpr int twk(int wv, int lane, int g) {
+        const int b = wv * 64 + g * 16 + (lane & 15);
+        return (b & (G::L16 - 1)) & (Ns - 1);
+    }
+    static constexpr int wr(int wv, int lane, int g, int i) {
+        const int n = lane & 15, kb = lane >> 4;
+        const int b = wv * 64 + g * 16 + n;
+        const int c = b >> (G::logL - 4), bb = b & (G::L16 - 1);
+        const int k = bb & (Ns - 1);
+        return G::idx(0, c, ((bb - k) << 4) + k + (4 * kb + i) * Ns);
+    }
+    static constexpr bool linear() {
+        for (int wv = 0; wv < G::TPP / 64; ++wv)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int g = 0; g < 4; ++g) {
+                    if (twk(wv, lane, g) - twk(wv, lane, 0) != twk(0, 0, g) - twk(0, 0, 0)) return false;
+                    for (int t = 0; t < 4; ++t)
+                        if (rd(wv, lane, g, t) - rd(wv, lane, 0, 0) != rd(0, 0, g, t) - rd(0, 0, 0, 0) ||
+                            wr(wv, lane, g, t) - wr(wv, lane, 0, 0) != wr(0, 0, g, t) - wr(0, 0, 0, 0))
+                            return false;
+                }
+        return true;
+    }
+    static constexpr bool LINEAR = linear();
+    struct Tab {
+        int rd[4][4], wr[4][4], tw[4];
+    };
+    static constexpr Tab tab() {
+        Tab r{};
+        for (int g = 0; g < 4; ++g) {
+            r.tw[g] = twk(0, 0, g) - twk(0, 0, 0);
+            for (int t = 0; t < 4; ++t) {
+                r.rd[g][t] = rd(0, 0, g, t) - rd(0, 0, 0, 0);
+                r.wr[g][t] = wr(0, 0, g, t) - wr(0, 0, 0, 0);
+            }
+        }
+        return r;
+    }
+};
+
 // Radix-16 pass I as in pass16 (same inputs, twiddles and output positions),
 // on the matrix cores.  Every pass, the last included, writes its outputs to
 // LDS; the last one's land in natural order.  PREC 1: MFMA_FP16, 2: FP16X2.
@@ -396,6 +452,13 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
     constexpr int GR = 4;  // groups of 16 butterflies per wave
     const int lane = lt & 63, wv = lt >> 6;
     const int n = lane & 15, kb = lane >> 4;
+    typedef Mfma16Pos<G, I> Pos;
+    constexpr typename Pos::Tab D = Pos::tab();
+    // this lane's (g, t) = (0, 0) positions (used where Pos::LINEAR)
+    const int b0 = wv * 64 + n;
+    const int c0 = b0 >> (G::logL - 4), bb0 = b0 & (G::L16 - 1), k0 = bb0 & (Ns - 1);
+    const int rd0 = G::idx(pol, c0, bb0 + 4 * kb * G::L16);
+    const int wr0 = G::idx(pol, c0, ((bb0 - k0) << 4) + k0 + 4 * kb * Ns);
     float2 x[GR][4];
 #pragma unroll
     for (int g = 0; g < GR; ++g) {
@@ -403,11 +466,11 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
         const int c = b >> (G::logL - 4), bb = b & (G::L16 - 1);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int a = G::idx(pol, c, bb + (4 * kb + t) * G::L16);
+            const int a = Pos::LINEAR ? rd0 + D.rd[g][t] : G::idx(pol, c, bb + (4 * kb + t) * G::L16);
             x[g][t] = make_float2(sre[a], sim[a]);
         }
         if (Ns > 1) {
-            const int k = bb & (Ns - 1);
+            const int k = Pos::LINEAR ? k0 + D.tw[g] : bb & (Ns - 1);
             const float2 *tk = tw + G::tw_off(I) + k * 15;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -471,7 +534,7 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
         const int base = ((bb - k) << 4) + k;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int a = G::idx(pol, c, base + (4 * kb + i) * Ns);
+            const int a = Pos::LINEAR ? wr0 + D.wr[g][i] : G::idx(pol, c, base + (4 * kb + i) * Ns);
             sre[a] = __builtin_amdgcn_ldexpf(yr[i], -sc);
             sim[a] = __builtin_amdgcn_ldexpf(yi[i], -sc);
         }
