@@ -508,7 +508,13 @@ __device__ __forceinline__ void pass16_mfma(float *sre, float *sim, int pol, int
             const unsigned hu = __builtin_bit_cast(unsigned, h);
             unsigned lu = 0;
             if constexpr (PREC == 2) {
-                const float2v r = xs - __builtin_convertvector(h, float2v);
+                // x - hi, exact (hi is x rounded to FP16), each in one
+                // mixed-precision FMA that widens its FP16 operand itself
+                // (instead of a conversion and a subtraction: same bits)
+                float rx, ry;
+                asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(rx) : "v"(hu), "v"(xs.x));
+                asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(ry) : "v"(hu), "v"(xs.y));
+                const float2v r = {rx, ry};
                 lu = __builtin_bit_cast(unsigned, __builtin_convertvector(r, half2v));
             }
             if (t == 0) { uh.x = hu; ul.x = lu; }
